@@ -1,0 +1,561 @@
+/*
+ * pft_oracle.c -- plain FP64 CPU oracle for the propagator hot path of
+ * K. T. Delaney and G. H. Fredrickson, "Polymer Field-Theory Simulations on
+ * Graphics Processing Units" (arXiv:1204.5434).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the slow, obviously-correct reference the
+ * GPU library is checked against.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header, table
+ * or constant with the GPU library and the GPU library never calls it.
+ *
+ * Everything is IEEE double precision (C99 double complex).  Fields are
+ * stored in C order [nx][ny][nz] (z fastest).  No FFT library is used: the
+ * discrete Fourier transform is either the O(M^2) definition written out
+ * (or_dft3_naive) or a plain recursive Cooley-Tukey FFT (or_fft3).
+ *
+ * Readings of points the paper leaves open (the q-dagger convention, the
+ * contour quadrature, the A/B junction, the update sign, the noise stream)
+ * are stated next to the function that takes them.
+ *
+ * Parity status: every function here is pinned by the CPU test suite
+ * (closed forms, invariants, Debye response, convergence order, brute-force
+ * DFT, numpy's Philox, finite differences); none is "parity unpinned".
+ */
+#include <complex.h>
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define OR_TWO_PI 6.283185307179586476925286766559
+
+/* Model and discretisation parameters.  Lengths in units of R_g, the contour
+ * normalised to [0, 1] (Sec. II, Eqs. (3)-(5)). */
+typedef struct {
+    int32_t nx, ny, nz;    /* grid points per axis                               */
+    double lx, ly, lz;     /* periodic box edges                                 */
+    int32_t ns;            /* contour steps, ds = 1/ns                           */
+    double f;              /* A-block fraction f_A (Eq. (8))                     */
+    double chiN;           /* chi_AB N (Eq. (3))                                 */
+    double C;              /* chain number density parameter (Eq. (3))           */
+    int32_t scheme;        /* 0 = Richardson split step (Eq. (12)), 1 = plain split */
+    int32_t naive_dft;     /* 1: use the O(M^2) DFT definition, 0: recursive FFT */
+} or_params;
+
+enum { OR_RQM4 = 0, OR_SPLIT2 = 1 };
+
+static int64_t grid_m(const or_params *p) { return (int64_t)p->nx * p->ny * p->nz; }
+
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int or_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Contour discretisation.                                                   */
+/*                                                                           */
+/* Reading of Eq. (8): the A block occupies s in [0, f], the B block [f, 1]. */
+/* The contour is cut into ns steps of ds = 1/ns.  When f*ns is not an       */
+/* integer, a node is inserted at s = f and the step that straddles it is    */
+/* split into an A sub-step of length f - n*ds and a B sub-step of length    */
+/* (n+1)*ds - f, so each step sees a single field and the block integrals of */
+/* Eq. (8) end exactly on a node.                                            */
+/*                                                                           */
+/* Outputs: h[j], blk[j] (0 = A, 1 = B) for steps j = 0..K-1; *junction = the */
+/* node index J with s_J = f.  Returns K.                                    */
+/* ------------------------------------------------------------------------ */
+int or_contour(int32_t ns, double f, double *h, int32_t *blk, int32_t *junction)
+{
+    const double ds = 1.0 / ns;
+    const double fn = f * ns;
+    const double r = floor(fn + 0.5);
+    int K = 0;
+    if (fabs(fn - r) <= 1e-9) {
+        const int na = (int)r;
+        for (int j = 0; j < ns; j++) {
+            h[K] = ds;
+            blk[K] = (j < na) ? 0 : 1;
+            K++;
+        }
+        *junction = na;
+    } else {
+        const int nstar = (int)floor(fn);
+        for (int j = 0; j < nstar; j++) { h[K] = ds; blk[K] = 0; K++; }
+        h[K] = f - nstar * ds; blk[K] = 0; K++;
+        h[K] = (nstar + 1) * ds - f; blk[K] = 1; K++;
+        for (int j = nstar + 1; j < ns; j++) { h[K] = ds; blk[K] = 1; K++; }
+        *junction = nstar + 1;
+    }
+    return K;
+}
+
+/* Composite trapezoid weights of each block on its own nodes (reading of the */
+/* contour integrals in Eq. (8)): an end node of a block gets half its one     */
+/* adjacent step, an interior node half of each of its two adjacent steps.    */
+/* tauA, tauB have K+1 entries (one per node); tauA is zero on B-only nodes.  */
+void or_trapezoid(int K, const double *h, const int32_t *blk, double *tauA, double *tauB)
+{
+    for (int j = 0; j <= K; j++) { tauA[j] = 0.0; tauB[j] = 0.0; }
+    for (int j = 0; j < K; j++) {
+        double *tau = (blk[j] == 0) ? tauA : tauB;
+        tau[j] += 0.5 * h[j];
+        tau[j + 1] += 0.5 * h[j];
+    }
+}
+
+/* Integer wave number of DFT index j on an axis of n points: j for j <= n/2, */
+/* j - n above.  Only its square enters the diffusion operator.               */
+int32_t or_mode(int32_t j, int32_t n) { return (j <= n / 2) ? j : j - n; }
+
+/* ------------------------------------------------------------------------ */
+/* Discrete Fourier transform.                                               */
+/* Forward: U[k] = sum_x u[x] exp(-2 pi i k.x / n) (sign = -1), unnormalised. */
+/* Inverse: sign = +1, also unnormalised (the 1/M lives in or_diffuse).      */
+/* ------------------------------------------------------------------------ */
+
+/* e^{sign 2 pi i a / n} with the angle reduced exactly in integers. */
+static cplx unit_root(int64_t a, int64_t n, int sign)
+{
+    int64_t r = a % n;
+    if (r < 0) r += n;
+    const double t = OR_TWO_PI * (double)r / (double)n;
+    return cos(t) + sign * sin(t) * I;
+}
+
+/* The definition written out: O(M^2) three-dimensional DFT. */
+void or_dft3_naive(const cplx *in, cplx *out, int32_t nx, int32_t ny, int32_t nz, int32_t sign)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < (int64_t)nx * ny * nz; k++) {
+        const int64_t kx = k / ((int64_t)ny * nz), ky = (k / nz) % ny, kz = k % nz;
+        cplx acc = 0.0;
+        for (int64_t x = 0; x < nx; x++)
+            for (int64_t y = 0; y < ny; y++)
+                for (int64_t z = 0; z < nz; z++) {
+                    /* phase = kx x/nx + ky y/ny + kz z/nz, summed over a common denominator */
+                    const int64_t den = (int64_t)nx * ny * nz;
+                    const int64_t num = kx * x * ny * nz + ky * y * nx * nz + kz * z * nx * ny;
+                    acc += in[(x * ny + y) * nz + z] * unit_root(num, den, sign);
+                }
+        out[k] = acc;
+    }
+}
+
+static int smallest_factor(int n)
+{
+    for (int p = 2; p * p <= n; p++)
+        if (n % p == 0) return p;
+    return n;
+}
+
+/*
+ * Recursive decimation-in-time Cooley-Tukey FFT of length n.
+ * x: input with element stride s; X: contiguous output of length n.
+ * tw[t] = e^{sign 2 pi i t / ntop}; W_n^a = tw[a * (ntop / n)].
+ * With p the smallest factor of n and m = n/p:
+ *   Y_r[k] = DFT_m of x[(i p + r) s] over i,
+ *   X[k + m q] = sum_r W_n^{r (k + m q)} Y_r[k].
+ */
+static void fft_rec(const cplx *x, ptrdiff_t s, cplx *X, int n, const cplx *tw, int ntop)
+{
+    if (n == 1) { X[0] = x[0]; return; }
+    const int p = smallest_factor(n);
+    const int m = n / p;
+    const int step = ntop / n;
+    if (p == n) {               /* prime length: the definition */
+        for (int k = 0; k < n; k++) {
+            cplx acc = 0.0;
+            for (int j = 0; j < n; j++) acc += x[j * s] * tw[(int64_t)((j * k) % n) * step];
+            X[k] = acc;
+        }
+        return;
+    }
+    for (int r = 0; r < p; r++) fft_rec(x + r * s, s * p, X + r * m, m, tw, ntop);
+    cplx t[64];
+    cplx *tmp = (p <= 64) ? t : (cplx *)malloc(sizeof(cplx) * p);
+    for (int k = 0; k < m; k++) {
+        for (int r = 0; r < p; r++) tmp[r] = X[r * m + k] * tw[(int64_t)((r * k) % n) * step];
+        for (int q = 0; q < p; q++) {
+            cplx acc = 0.0;
+            for (int r = 0; r < p; r++) acc += tmp[r] * tw[(int64_t)((r * q) % p) * m * step];
+            X[k + m * q] = acc;
+        }
+    }
+    if (tmp != t) free(tmp);
+}
+
+/* 1-D FFT along one axis of a [nx][ny][nz] array, in place, all lines. */
+static void fft_axis(cplx *a, int32_t nx, int32_t ny, int32_t nz, int axis, int sign)
+{
+    const int n = (axis == 0) ? nx : (axis == 1) ? ny : nz;
+    const ptrdiff_t stride = (axis == 0) ? (ptrdiff_t)ny * nz : (axis == 1) ? nz : 1;
+    const int64_t nlines = (int64_t)nx * ny * nz / n;
+    cplx *tw = (cplx *)malloc(sizeof(cplx) * n);
+    for (int t = 0; t < n; t++) tw[t] = unit_root(t, n, sign);
+    #pragma omp parallel
+    {
+        cplx *in = (cplx *)malloc(sizeof(cplx) * n);
+        cplx *out = (cplx *)malloc(sizeof(cplx) * n);
+        #pragma omp for schedule(static)
+        for (int64_t l = 0; l < nlines; l++) {
+            ptrdiff_t base;
+            if (axis == 2) base = l * nz;
+            else if (axis == 1) base = (l / nz) * (ptrdiff_t)ny * nz + (l % nz);
+            else base = l;
+            for (int i = 0; i < n; i++) in[i] = a[base + i * stride];
+            fft_rec(in, 1, out, n, tw, n);
+            for (int i = 0; i < n; i++) a[base + i * stride] = out[i];
+        }
+        free(in);
+        free(out);
+    }
+    free(tw);
+}
+
+/* Three-dimensional FFT in place: the 1-D transform along z, y and x. */
+void or_fft3(cplx *a, int32_t nx, int32_t ny, int32_t nz, int32_t sign)
+{
+    fft_axis(a, nx, ny, nz, 2, sign);
+    fft_axis(a, nx, ny, nz, 1, sign);
+    fft_axis(a, nx, ny, nz, 0, sign);
+}
+
+static void dft3(const or_params *p, cplx *u, int sign)
+{
+    if (p->naive_dft) {
+        const int64_t M = grid_m(p);
+        cplx *t = (cplx *)malloc(sizeof(cplx) * M);
+        or_dft3_naive(u, t, p->nx, p->ny, p->nz, sign);
+        memcpy(u, t, sizeof(cplx) * M);
+        free(t);
+    } else {
+        or_fft3(u, p->nx, p->ny, p->nz, sign);
+    }
+}
+
+/* |k|^2 of DFT index (jx, jy, jz): sum over axes of (2 pi m / L)^2. */
+static double ksq(const or_params *p, int64_t jx, int64_t jy, int64_t jz)
+{
+    const double kx = OR_TWO_PI * or_mode((int32_t)jx, p->nx) / p->lx;
+    const double ky = OR_TWO_PI * or_mode((int32_t)jy, p->ny) / p->ly;
+    const double kz = OR_TWO_PI * or_mode((int32_t)jz, p->nz) / p->lz;
+    return kx * kx + ky * ky + kz * kz;
+}
+
+/* |k|^2 on the whole grid, natural DFT order (a test hook for the k-grid). */
+void or_ksq_grid(const or_params *p, double *out)
+{
+    for (int64_t jx = 0; jx < p->nx; jx++)
+        for (int64_t jy = 0; jy < p->ny; jy++)
+            for (int64_t jz = 0; jz < p->nz; jz++)
+                out[(jx * p->ny + jy) * p->nz + jz] = ksq(p, jx, jy, jz);
+}
+
+/* The diffusion operator exp(h Laplacian) of Eq. (5), exact on the Fourier */
+/* basis: u <- IDFT( e^{-|k|^2 h} DFT(u) ) / M.                              */
+void or_diffuse(const or_params *p, double h, cplx *u)
+{
+    const int64_t M = grid_m(p);
+    dft3(p, u, -1);
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < M; k++) {
+        const int64_t jx = k / ((int64_t)p->ny * p->nz), jy = (k / p->nz) % p->ny, jz = k % p->nz;
+        u[k] *= exp(-ksq(p, jx, jy, jz) * h) / (double)M;
+    }
+    dft3(p, u, +1);
+}
+
+/* u <- e^{-w a} u, the field operator of the split step, pointwise. */
+static void mul_field_exp(cplx *u, const cplx *w, double a, int64_t M)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < M; x++) u[x] *= cexp(-w[x] * a);
+}
+
+/*
+ * One contour step of length h in the field w, q_out = T_h(q_in; w).
+ * Plain split (second order):  T = E_{h/2} D_h E_{h/2}.
+ * Richardson split step, Eq. (12):
+ *   T = -(1/3) [ E_{h/2} D_h E_{h/2} - 4 E_{h/4} D_{h/2} E_{h/2} D_{h/2} E_{h/4} ],
+ * with E_a = e^{-w a} and D_a the diffusion operator; operators act right to left.
+ * work must hold 2*M values.
+ */
+void or_step(const or_params *p, int32_t scheme, double h, const cplx *w,
+             const cplx *qin, cplx *qout, cplx *work)
+{
+    const int64_t M = grid_m(p);
+    cplx *full = work, *half = work + M;
+    /* one full step: E_{h/2} D_h E_{h/2} q */
+    memcpy(full, qin, sizeof(cplx) * M);
+    mul_field_exp(full, w, h / 2, M);
+    or_diffuse(p, h, full);
+    mul_field_exp(full, w, h / 2, M);
+    if (scheme == OR_SPLIT2) {
+        memcpy(qout, full, sizeof(cplx) * M);
+        return;
+    }
+    /* two half steps: E_{h/4} D_{h/2} E_{h/2} D_{h/2} E_{h/4} q */
+    memcpy(half, qin, sizeof(cplx) * M);
+    mul_field_exp(half, w, h / 4, M);
+    or_diffuse(p, h / 2, half);
+    mul_field_exp(half, w, h / 2, M);
+    or_diffuse(p, h / 2, half);
+    mul_field_exp(half, w, h / 4, M);
+    for (int64_t x = 0; x < M; x++) qout[x] = -(1.0 / 3.0) * (full[x] - 4.0 * half[x]);
+}
+
+/* Block fields w_A = i w_+ - w_-, w_B = i w_+ + w_- (Sec. II, after Eq. (3)). */
+void or_block_fields(const or_params *p, const cplx *wp, const cplx *wm, cplx *wA, cplx *wB)
+{
+    const int64_t M = grid_m(p);
+    for (int64_t x = 0; x < M; x++) {
+        wA[x] = I * wp[x] - wm[x];
+        wB[x] = I * wp[x] + wm[x];
+    }
+}
+
+/*
+ * Forward and conjugate propagators (Eq. (5) with the initial conditions that
+ * follow it).  Reading of the q-dagger convention of Eq. (8): q-dagger runs on
+ * its own contour s' = 1 - s from q-dagger(s'=0) = 1 at the B end, so node j
+ * of q pairs with node K-j of q-dagger.
+ *   q_0 = 1,  q_{j+1} = T_{h_j}(q_j; w_{blk(j)}),
+ *   qd_0 = 1, qd_{i+1} = T_{h_{K-1-i}}(qd_i; w_{blk(K-1-i)}).
+ * qs and qds hold (K+1)*M values each (slice j at offset j*M); either may be
+ * NULL to skip that sweep.  Returns K.
+ */
+int or_propagate(const or_params *p, const cplx *wp, const cplx *wm, cplx *qs, cplx *qds)
+{
+    const int64_t M = grid_m(p);
+    double *h = (double *)malloc(sizeof(double) * (p->ns + 2));
+    int32_t *blk = (int32_t *)malloc(sizeof(int32_t) * (p->ns + 2));
+    int32_t J;
+    const int K = or_contour(p->ns, p->f, h, blk, &J);
+    cplx *wA = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *wB = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *work = (cplx *)malloc(sizeof(cplx) * 2 * M);
+    or_block_fields(p, wp, wm, wA, wB);
+    if (qs) {
+        for (int64_t x = 0; x < M; x++) qs[x] = 1.0;
+        for (int j = 0; j < K; j++)
+            or_step(p, p->scheme, h[j], blk[j] == 0 ? wA : wB, qs + (int64_t)j * M,
+                    qs + (int64_t)(j + 1) * M, work);
+    }
+    if (qds) {
+        for (int64_t x = 0; x < M; x++) qds[x] = 1.0;
+        for (int i = 0; i < K; i++) {
+            const int j = K - 1 - i;
+            or_step(p, p->scheme, h[j], blk[j] == 0 ? wA : wB, qds + (int64_t)i * M,
+                    qds + (int64_t)(i + 1) * M, work);
+        }
+    }
+    free(h); free(blk); free(wA); free(wB); free(work);
+    return K;
+}
+
+/*
+ * Partition function and segment densities from stored propagators.
+ * Q = (1/M) sum_x q_K(x)   (Eq. (4), the integral as the grid mean).
+ * Qnode[j] = (1/M) sum_x q_j(x) qd_{K-j}(x) for every node (equal to Q in
+ * exact arithmetic; a diagnostic of the sweeps).
+ * phi_A = (1/Q) sum_j tauA_j q_j qd_{K-j},  phi_B likewise (Eq. (8) divided by
+ * rho_0, with the trapezoid weights of or_trapezoid).
+ */
+void or_densities(const or_params *p, const cplx *qs, const cplx *qds,
+                  cplx *phiA, cplx *phiB, cplx *Q, cplx *Qnode)
+{
+    const int64_t M = grid_m(p);
+    double *h = (double *)malloc(sizeof(double) * (p->ns + 2));
+    int32_t *blk = (int32_t *)malloc(sizeof(int32_t) * (p->ns + 2));
+    int32_t J;
+    const int K = or_contour(p->ns, p->f, h, blk, &J);
+    double *tauA = (double *)malloc(sizeof(double) * (K + 1));
+    double *tauB = (double *)malloc(sizeof(double) * (K + 1));
+    or_trapezoid(K, h, blk, tauA, tauB);
+
+    cplx sum = 0.0;
+    for (int64_t x = 0; x < M; x++) sum += qs[(int64_t)K * M + x];
+    *Q = sum / (double)M;
+    if (Qnode) {
+        for (int j = 0; j <= K; j++) {
+            cplx s = 0.0;
+            for (int64_t x = 0; x < M; x++) s += qs[(int64_t)j * M + x] * qds[(int64_t)(K - j) * M + x];
+            Qnode[j] = s / (double)M;
+        }
+    }
+    #pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < M; x++) {
+        cplx a = 0.0, b = 0.0;
+        for (int j = 0; j <= K; j++) {
+            const cplx prod = qs[(int64_t)j * M + x] * qds[(int64_t)(K - j) * M + x];
+            a += tauA[j] * prod;
+            b += tauB[j] * prod;
+        }
+        phiA[x] = a / *Q;
+        phiB[x] = b / *Q;
+    }
+    free(h); free(blk); free(tauA); free(tauB);
+}
+
+/*
+ * Diblock Hamiltonian, Eq. (3), on the grid (integral -> dV * sum):
+ *   H = C dV sum_x [ w_-^2 / chiN - i w_+ ] - C V log Q,
+ * with dV = V/M, V = lx ly lz and the principal branch of the complex log.
+ * Also returns the intensive h = H / (C V).
+ */
+void or_hamiltonian(const or_params *p, const cplx *wp, const cplx *wm, double Qre, double Qim,
+                    cplx *H, cplx *hint)
+{
+    const cplx Q = Qre + Qim * I;
+    const int64_t M = grid_m(p);
+    const double V = p->lx * p->ly * p->lz;
+    const double dV = V / (double)M;
+    cplx s = 0.0;
+    for (int64_t x = 0; x < M; x++) s += wm[x] * wm[x] / p->chiN - I * wp[x];
+    *H = p->C * dV * s - p->C * V * clog(Q);
+    *hint = *H / (p->C * V);
+}
+
+/*
+ * Mean-field forces (the functional derivatives of Eq. (3) per unit C dV,
+ * written in terms of phi = rho/rho_0; the unnumbered mean-field equations
+ * of Sec. II):
+ *   F_+ = i (phi_A + phi_B - 1),   F_- = 2 w_- / chiN + phi_B - phi_A.
+ */
+void or_forces(const or_params *p, const cplx *wm, const cplx *phiA, const cplx *phiB,
+               cplx *Fp, cplx *Fm)
+{
+    const int64_t M = grid_m(p);
+    for (int64_t x = 0; x < M; x++) {
+        Fp[x] = I * (phiA[x] + phiB[x] - 1.0);
+        Fm[x] = 2.0 * wm[x] / p->chiN + phiB[x] - phiA[x];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11, "Parallel random       */
+/* numbers: as easy as 1, 2, 3"): ten rounds of two 64x64->128 multiplies   */
+/* with a Weyl-sequence key schedule.                                       */
+/* ------------------------------------------------------------------------ */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    const unsigned __int128 prod = (unsigned __int128)a * b;
+    *hi = (uint64_t)(prod >> 64);
+    *lo = (uint64_t)prod;
+}
+
+void or_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; round++) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(M0, c0, &hi0, &lo0);
+        mulhilo64(M1, c2, &hi1, &lo1);
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0, 1), never 0: the top 53 bits plus one half, times 2^-53. */
+static double u01(uint64_t x) { return ((double)(x >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+/*
+ * Standard normal deviates for one field at one Langevin step.
+ * Stream layout: key = (seed, replica); the block of four sites 4g..4g+3 of
+ * field `field` at step `step` uses counter (g, field, step, 0); its four
+ * 64-bit words become two Box-Muller pairs (u0,u1) -> (z0,z1), (u2,u3) -> (z2,z3),
+ * and site 4g+r takes z_r.
+ */
+void or_gaussian(uint64_t seed, uint64_t replica, uint64_t step, int32_t field, int64_t M, double *xi)
+{
+    const uint64_t key[2] = {seed, replica};
+    for (int64_t g = 0; 4 * g < M; g++) {
+        const uint64_t ctr[4] = {(uint64_t)g, (uint64_t)field, step, 0};
+        uint64_t r[4];
+        or_philox4x64_10(ctr, key, r);
+        double z[4];
+        for (int pair = 0; pair < 2; pair++) {
+            const double a = u01(r[2 * pair]), b = u01(r[2 * pair + 1]);
+            const double rad = sqrt(-2.0 * log(a));
+            z[2 * pair] = rad * cos(OR_TWO_PI * b);
+            z[2 * pair + 1] = rad * sin(OR_TWO_PI * b);
+        }
+        for (int rr = 0; rr < 4 && 4 * g + rr < M; rr++) xi[4 * g + rr] = z[rr];
+    }
+}
+
+/*
+ * Explicit Euler-Maruyama step of the field equation of motion, Eq. (9), for
+ * both fields at once from the forces of the current fields:
+ *   w_+ <- w_+ - lam_+ dt F_+ + s_+ xi_+,   w_- <- w_- - lam_- dt F_- + s_- xi_-,
+ * with xi real standard normals and s^2 = 2 lam dt / (C dV), the discrete noise
+ * variance given after Eq. (10) for forces taken per unit C dV.  Reading: the
+ * fields are not Wick rotated (Sec. III), so the drift is -lam F for both;
+ * noise = 0 gives the deterministic (SCFT) relaxation.
+ */
+void or_em_update(const or_params *p, cplx *wp, cplx *wm, const cplx *phiA, const cplx *phiB,
+                  double dt, double lam_p, double lam_m, int32_t noise,
+                  uint64_t seed, uint64_t replica, uint64_t step)
+{
+    const int64_t M = grid_m(p);
+    const double dV = p->lx * p->ly * p->lz / (double)M;
+    cplx *Fp = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *Fm = (cplx *)malloc(sizeof(cplx) * M);
+    double *xp = (double *)calloc(M, sizeof(double));
+    double *xm = (double *)calloc(M, sizeof(double));
+    or_forces(p, wm, phiA, phiB, Fp, Fm);
+    if (noise) {
+        or_gaussian(seed, replica, step, 0, M, xp);
+        or_gaussian(seed, replica, step, 1, M, xm);
+    }
+    const double sp = noise ? sqrt(2.0 * lam_p * dt / (p->C * dV)) : 0.0;
+    const double sm = noise ? sqrt(2.0 * lam_m * dt / (p->C * dV)) : 0.0;
+    for (int64_t x = 0; x < M; x++) {
+        wp[x] = wp[x] - lam_p * dt * Fp[x] + sp * xp[x];
+        wm[x] = wm[x] - lam_m * dt * Fm[x] + sm * xm[x];
+    }
+    free(Fp); free(Fm); free(xp); free(xm);
+}
+
+/*
+ * One full field evaluation: propagators, Q, per-node Q, densities and H.
+ * Convenience wrapper over the functions above.  Qnode may be NULL.
+ */
+int or_evaluate(const or_params *p, const cplx *wp, const cplx *wm,
+                cplx *phiA, cplx *phiB, cplx *Q, cplx *Qnode, cplx *H, cplx *hint)
+{
+    const int64_t M = grid_m(p);
+    const int64_t K = p->ns + 1; /* upper bound on the step count */
+    cplx *qs = (cplx *)malloc(sizeof(cplx) * (K + 1) * M);
+    cplx *qds = (cplx *)malloc(sizeof(cplx) * (K + 1) * M);
+    if (!qs || !qds) { free(qs); free(qds); return -1; }
+    const int k = or_propagate(p, wp, wm, qs, qds);
+    or_densities(p, qs, qds, phiA, phiB, Q, Qnode);
+    or_hamiltonian(p, wp, wm, creal(*Q), cimag(*Q), H, hint);
+    free(qs); free(qds);
+    return k;
+}
