@@ -1,0 +1,209 @@
+/*
+ * pft.h -- C ABI of the MI355X (gfx950) propagator library for polymer
+ * field theory: the pseudo-spectral operator-split solution of the modified
+ * diffusion equation for the chain propagators q and q-dagger of an
+ * incompressible AB diblock melt in a periodic box, the contour-integrated
+ * segment densities, the single-chain partition function Q, the Hamiltonian,
+ * and one explicit field (SCFT / complex-Langevin) step.
+ *
+ * Paper: K. T. Delaney and G. H. Fredrickson, "Polymer Field-Theory
+ * Simulations on Graphics Processing Units", arXiv:1204.5434.
+ *
+ * Conventions that hold for every entry point:
+ *  - Fields, densities and debug arrays are HIP DEVICE memory owned by the
+ *    caller: complex128, interleaved (re, im) doubles, C order [nx][ny][nz]
+ *    (z fastest), 16-byte aligned.  Scalar results (Q, H, ...) are written to
+ *    caller-owned DEVICE memory as complex128 (two doubles), so no call needs
+ *    a host synchronisation.
+ *  - The context owns every internal buffer (propagator slice stores, field
+ *    operator tables, diffusion factors, work arrays, reduction scratch).
+ *  - Work is enqueued asynchronously on the HIP stream given to pft_create.
+ *    Device pointers passed in must stay valid until that work completes.
+ *  - No call throws or aborts.  Each returns a pft_status; on failure
+ *    pft_last_error(ctx) holds a message (owned by the context).  Invalid
+ *    arguments are rejected before anything is enqueued.
+ *  - Propagator precision: PFT_C128 runs the propagators and FFTs in complex
+ *    double; PFT_C64 in complex float.  Field operator tables, twiddles and
+ *    diffusion factors are computed in double and rounded once.  Q, log Q,
+ *    the contour sums, H and the field update are always double precision
+ *    with compensated (Neumaier) summation.
+ */
+#ifndef PFT_H
+#define PFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pft_ctx pft_ctx;
+
+typedef enum {
+    PFT_OK = 0,
+    PFT_E_INVALID = 1,     /* bad argument (null/misaligned pointer, bad parameter) */
+    PFT_E_UNSUPPORTED = 2, /* grid size without a kernel, or an unsupported mode      */
+    PFT_E_NOMEM = 3,       /* device allocation failed; nothing is leaked             */
+    PFT_E_DEVICE = 4,      /* a HIP runtime call failed (the message names it)        */
+    PFT_E_NONFINITE = 5,   /* a non-finite Q was produced (reported by status_flags)  */
+    PFT_E_STATE = 6        /* call order violated, e.g. densities before propagate     */
+} pft_status;
+
+typedef enum { PFT_C128 = 0, PFT_C64 = 1 } pft_precision;
+
+/* PFT_RQM4: the Richardson-extrapolated split step of Eq. (12) (Sec. III),
+ *   T_h = (4/3) E_{h/4} D_{h/2} E_{h/2} D_{h/2} E_{h/4} - (1/3) E_{h/2} D_h E_{h/2},
+ * globally fourth order in the contour step.  PFT_SPLIT2: the plain
+ * second-order split step E_{h/2} D_h E_{h/2}.  E_a = exp(-w a), D_h =
+ * exp(h Laplacian) applied in Fourier space. */
+typedef enum { PFT_RQM4 = 0, PFT_SPLIT2 = 1 } pft_scheme;
+
+/* Model and discretisation.  Lengths in units of R_g; the contour is
+ * normalised to [0, 1] and cut into ns steps (Sec. II, Eqs. (3)-(5)). */
+typedef struct {
+    int32_t nx, ny, nz; /* grid points per axis; each must be one of
+                           8 12 16 20 24 32 40 48 64 80 96 128 192 256        */
+    double lx, ly, lz;  /* periodic box edges, > 0                            */
+    int32_t ns;         /* contour steps, >= 2                                */
+    double f;           /* A-block fraction, 0 < f < 1 (Eq. (8))              */
+    double chiN;        /* Flory parameter times N, > 0 (Eq. (3))             */
+    double C;           /* chain number density parameter, > 0 (Eq. (3))      */
+    int32_t precision;  /* pft_precision                                      */
+    int32_t scheme;     /* pft_scheme                                         */
+} pft_params;
+
+/* One explicit Euler-Maruyama step of the field equation of motion, Eq. (9):
+ *   w_+ <- w_+ - lambda_+ dt F_+ + s_+ xi_+,  w_- <- w_- - lambda_- dt F_- + s_- xi_-,
+ * F_+ = i (phi_A + phi_B - 1), F_- = 2 w_- / chiN + phi_B - phi_A, s^2 =
+ * 2 lambda dt / (C dV) (the discrete noise variance stated after Eq. (10)),
+ * xi real standard normals from Philox4x64-10 keyed by (seed, replica) with
+ * counter (site / 4, field, step, 0).  noise = 0 gives SCFT relaxation. */
+typedef struct {
+    double dt, lambda_plus, lambda_minus;
+    uint64_t seed, replica, step;
+    int32_t noise;
+} pft_step;
+
+/* Create a context for one parameter set on the current HIP device.
+ * hip_stream: a hipStream_t (NULL = the default stream).  Allocates the two
+ * propagator slice stores ((K+1) * M values each, K = ns or ns+1) and all
+ * tables.  Errors: PFT_E_INVALID (bad parameter; *out = NULL),
+ * PFT_E_UNSUPPORTED (axis length without a kernel), PFT_E_NOMEM, PFT_E_DEVICE.
+ * On failure *out is NULL and nothing stays allocated. */
+pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out);
+
+/* Release everything the context owns (synchronises its stream). NULL is a no-op. */
+void pft_destroy(pft_ctx* ctx);
+
+/* Last error message of the context ("" if none); valid until the next call. */
+const char* pft_last_error(const pft_ctx* ctx);
+
+/* Static name of a status code. */
+const char* pft_status_string(pft_status status);
+
+/* Host-only contour plan (no GPU needed).  Reading of Eq. (8): ns steps of
+ * 1/ns; when f*ns is not an integer the step straddling s = f is split into
+ * an A sub-step f - n*ds and a B sub-step (n+1)*ds - f.  Writes the step
+ * lengths h[K] and blocks blk[K] (0 = A, 1 = B; arrays of ns+1 entries) and
+ * the junction node index *junction (s_J = f).  Returns K, or -1 on invalid
+ * arguments. */
+int32_t pft_contour_plan(int32_t ns, double f, double* h, int32_t* blk, int32_t* junction);
+
+/* Number of contour steps K of the context (ns or ns+1). */
+int32_t pft_num_steps(const pft_ctx* ctx);
+
+/* Solve the modified diffusion equation, Eq. (5), for q (from q = 1 at s = 0)
+ * and q-dagger (from 1 at s = 1) in the fields w_A = i w_+ - w_-,
+ * w_B = i w_+ + w_- (Sec. II), storing every contour node, and reduce
+ * Q = (1/M) sum_x q(x, 1) (Eq. (4)).  w_plus, w_minus: [nx][ny][nz]
+ * complex128, read during the call's GPU work only.  Errors: PFT_E_INVALID. */
+pft_status pft_propagate(pft_ctx* ctx, const double* w_plus, const double* w_minus);
+
+/* Segment densities of Eq. (8) divided by rho_0, from the stored
+ * propagators of the last pft_propagate: phi_A = (1/Q) sum_j tauA_j q_j qd_{K-j}
+ * (trapezoid weights per block, compensated FP64 sums), phi_B likewise.
+ * phi_a, phi_b: [nx][ny][nz] complex128 out.  Q: 2 doubles out (may be NULL).
+ * Errors: PFT_E_INVALID, PFT_E_STATE (no propagate yet). */
+pft_status pft_densities(pft_ctx* ctx, double* phi_a, double* phi_b, double* Q);
+
+/* Hamiltonian of Eq. (3) on the grid, H = C dV sum_x [w_-^2/chiN - i w_+]
+ * - C V Log Q (principal branch), with Q from the last pft_propagate (which
+ * must have used these fields).  H, h_intensive (= H / (C V)): 2 doubles out
+ * each (h_intensive may be NULL).  Errors: PFT_E_INVALID, PFT_E_STATE. */
+pft_status pft_hamiltonian(pft_ctx* ctx, const double* w_plus, const double* w_minus, double* H,
+                           double* h_intensive);
+
+/* One field step: propagate, densities, H (all of the INPUT fields), then the
+ * update of pft_step in place on w_plus, w_minus.  phi_a, phi_b, Q, H may be
+ * NULL (internal buffers are used).  Errors: PFT_E_INVALID. */
+pft_status pft_cl_step(pft_ctx* ctx, double* w_plus, double* w_minus, const pft_step* step,
+                       double* phi_a, double* phi_b, double* Q, double* H);
+
+/* Per-node diagnostic Qnode[j] = (1/M) sum_x q_j(x) qd_{K-j}(x), j = 0..K,
+ * from the last propagate; equal to Q in exact arithmetic for every node
+ * because each split step is complex-symmetric.  qnode: 2*(K+1) doubles of
+ * device memory.  Errors: PFT_E_INVALID, PFT_E_STATE. */
+pft_status pft_node_q(pft_ctx* ctx, double* qnode);
+
+/* Copy node `node` (0..K) of q (which = 0) or q-dagger (which = 1) from the
+ * last propagate into out ([nx][ny][nz] complex128, device), widening c64.
+ * Errors: PFT_E_INVALID, PFT_E_STATE. */
+pft_status pft_get_slice(pft_ctx* ctx, int32_t which, int32_t node, double* out);
+
+/* Apply contour step `step_index` (0..K-1, forward numbering) of the current
+ * fields to an arbitrary q: q_out = T_{h_j}(q_in; w_{blk(j)}), with the same
+ * kernels the sweeps use.  q_in, q_out: [nx][ny][nz] complex128 device (may
+ * alias).  Needs a prior pft_propagate.  Errors: PFT_E_INVALID, PFT_E_STATE. */
+pft_status pft_apply_step(pft_ctx* ctx, int32_t step_index, const double* q_in, double* q_out);
+
+/* Diffusion operator D_h = exp(h Laplacian) of Eq. (5) applied in place to
+ * u ([nx][ny][nz] complex128, device), through the same axis passes the
+ * sweeps use (in the context's precision).  Errors: PFT_E_INVALID. */
+pft_status pft_diffuse(pft_ctx* ctx, double* u, double h);
+
+/* Squared integer wave numbers m_x^2 + m_y^2 + m_z^2 of every grid point in
+ * natural DFT order, m(j) = j for j <= n/2 else j - n.  m2_out: M int32 of
+ * HOST memory.  Host-only; needs no GPU work.  Errors: PFT_E_INVALID. */
+pft_status pft_debug_kgrid(const pft_ctx* ctx, int32_t* m2_out);
+
+/* Status flags accumulated on the device since creation (bit 0: a non-finite
+ * Q).  Synchronises the stream.  Returns PFT_E_NONFINITE if bit 0 is set. */
+pft_status pft_status_flags(pft_ctx* ctx, uint32_t* flags);
+
+/* Noise stream test hooks (no context): the raw Philox4x64-10 words
+ * (4 per block of 4 sites, 4*ceil(M/4) uint64 out) and the standard normals
+ * (M doubles out) the field update draws for one field at one step.  Device
+ * output, enqueued on hip_stream.  Errors: PFT_E_INVALID, PFT_E_DEVICE. */
+pft_status pft_noise_words(uint64_t seed, uint64_t replica, uint64_t step, int32_t field, int64_t M,
+                           uint64_t* out, void* hip_stream);
+pft_status pft_noise_normals(uint64_t seed, uint64_t replica, uint64_t step, int32_t field,
+                             int64_t M, double* out, void* hip_stream);
+
+/* Kernel kinds reported by the profiling calls below. */
+typedef enum {
+    PFT_K_TABLES = 0,  /* field operator tables exp(-w h/4)                     */
+    PFT_K_ZPASS = 1,   /* z-axis pass: completes one step and starts the next    */
+    PFT_K_YPASS = 2,   /* y-axis passes                                          */
+    PFT_K_XPASS = 3,   /* x-axis pass                                            */
+    PFT_K_DENSITY = 4, /* contour-weighted q * q-dagger reduction               */
+    PFT_K_REDUCE = 5,  /* spatial reductions (Q, H, per-node Q) and the update   */
+    PFT_K_COUNT = 6
+} pft_kernel_kind;
+
+/* Per-kernel timing for roofline measurement.  Between pft_profile_begin and
+ * pft_profile_end, every kernel the context launches is bracketed by a pair
+ * of HIP events recorded on the context's stream.  pft_profile_end
+ * synchronises the stream and writes, per pft_kernel_kind (arrays of
+ * PFT_K_COUNT entries, host memory): the summed event-measured duration in
+ * milliseconds, the number of launches, and the summed algorithmic bytes
+ * (the bytes each launch must read and write given its inputs and outputs,
+ * each array counted once).  Any output pointer may be NULL.
+ * Errors: PFT_E_INVALID, PFT_E_STATE (end without begin), PFT_E_DEVICE. */
+pft_status pft_profile_begin(pft_ctx* ctx);
+pft_status pft_profile_end(pft_ctx* ctx, double* ms, int64_t* launches, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFT_H */

@@ -1,0 +1,247 @@
+// HIP kernels of the propagator hot path (gfx950, 64-lane wavefronts).
+//
+// One contour step of the Richardson split step, Eq. (12), is
+//   q' = (4/3) E4 D_{h/2} E2 D_{h/2} E4 q  -  (1/3) E2 D_h E2 q,
+// with E4 = exp(-w h/4), E2 = E4^2 and D_a = Dz Dy Dx the separable
+// diffusion operator.  Because the axis operators commute and act on whole
+// lines, a step runs as four memory passes over two work arrays
+// U (half-step path) and V (full-step path):
+//
+//   Z (step j-1 -> j) : U = Dz_{h/2}(E4 q_j),          V = Dz_h(E2 q_j)
+//   Y1                : U = Dy_{h/2} U,                V = Dy_h V
+//   X                 : U = Dx_{h/2}(E2 Dx_{h/2} U),   V = E2 Dx_h V
+//   Y2                : U = Dy_{h/2} U
+//   Z (step j -> j+1) : q_{j+1} = (4 E4 Dz_{h/2} U - V) / 3, stored, and the
+//                       next step's U and V are started from it in the same pass.
+//
+// The plain split step uses V alone: Z (q_{j+1} = E2 V; V = Dz_h(E2 q)), Y, X.
+// Every axis pass holds its lines on chip (registers plus one LDS exchange per
+// transform direction), so each pass reads and writes each array once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft.h"
+
+namespace pft {
+
+enum { kSchemeRQM4 = 0, kSchemeSplit2 = 1 };
+
+// ------------------------------------------------------------------ z pass --
+template <typename T>
+struct ZArgs {
+    int64_t nlines;   // nx * ny lines of nz contiguous points
+    cx<T>* U;
+    cx<T>* V;
+    const cx<T>* qin; // start value when there is no previous step (NULL: q = 1)
+    cx<T>* qout;      // where the completed q is stored (NULL: not stored)
+    int has_prev, has_next, scheme;
+    const cx<T>* Ep;  // E4 table of the step being completed (NULL: E = 1)
+    const T* gh_p;    // its z factor for h/2
+    const cx<T>* En;  // E4 table of the step being started (NULL: E = 1)
+    const T* gh_n;    // its z factors for h/2 and h
+    const T* gf_n;
+};
+
+template <int N1, int N2>
+struct LayZ {
+    int l;
+    __device__ __forceinline__ int operator()(int k1, int n2) const { return (l * N1 + k1) * (N2 + 1) + n2; }
+};
+
+template <int N1, int N2>
+struct ZShape {
+    static constexpr int kLines = (N2 >= 64) ? 1 : 64 / N2;  // lines per workgroup
+    static constexpr int kThreads = kLines * N2;
+    static constexpr int kLds = (N2 == 1) ? 0 : kLines * N1 * (N2 + 1);  // elements
+};
+
+template <typename T, int N1, int N2>
+__global__ __launch_bounds__((ZShape<N1, N2>::kThreads)) void k_zpass(ZArgs<T> A)
+{
+    constexpr int N = N1 * N2;
+    constexpr int LPW = ZShape<N1, N2>::kLines;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int t = tid % N2, l = tid / N2;
+    const int64_t line = (int64_t)blockIdx.x * LPW + l;
+    const bool act = line < A.nlines;
+    const int64_t base = line * N + t;
+    const LayZ<N1, N2> lay{l};
+
+    auto load = [&](const cx<T>* p, cx<T>(&r)[N1]) {
+        if (act) {
+            sfor<0, N1>([&](auto I) { r[decltype(I)::value] = p[base + decltype(I)::value * N2]; });
+        } else {
+            sfor<0, N1>([&](auto I) { r[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+        }
+    };
+    auto store = [&](cx<T>* p, const cx<T>(&r)[N1]) {
+        if (act) sfor<0, N1>([&](auto I) { p[base + decltype(I)::value * N2] = r[decltype(I)::value]; });
+    };
+
+    cx<T> q[N1];
+    if (A.has_prev) {
+        if (A.scheme == kSchemeRQM4) {
+            load(A.U, q);
+            diffuse<N1, N2>(q, t, sh, lay, A.gh_p);
+            constexpr T third = T(1.0 / 3.0);
+            if (act) {
+                sfor<0, N1>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const int64_t o = base + i * N2;
+                    const cx<T> u = A.Ep ? q[i] * A.Ep[o] : q[i];
+                    q[i] = third * (T(4) * u - A.V[o]);
+                });
+            }
+        } else {
+            load(A.V, q);
+            if (A.Ep && act) {
+                sfor<0, N1>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const cx<T> e = A.Ep[base + i * N2];
+                    q[i] = q[i] * (e * e);
+                });
+            }
+        }
+    } else if (A.qin) {
+        load(A.qin, q);
+    } else {
+        sfor<0, N1>([&](auto I) { q[decltype(I)::value] = cx<T>{T(1), T(0)}; });
+    }
+    if (A.qout) store(A.qout, q);
+
+    if (A.has_next) {
+        // q <- E4 q (half path start) and w <- E4 E4 q (full path start)
+        cx<T> w[N1];
+        if (A.En && act) {
+            sfor<0, N1>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const cx<T> e = A.En[base + i * N2];
+                q[i] = q[i] * e;
+                w[i] = q[i] * e;
+            });
+        } else {
+            sfor<0, N1>([&](auto I) { w[decltype(I)::value] = q[decltype(I)::value]; });
+        }
+        if (A.scheme == kSchemeRQM4) {
+            diffuse<N1, N2>(q, t, sh, lay, A.gh_n);
+            store(A.U, q);
+        }
+        diffuse<N1, N2>(w, t, sh, lay, A.gf_n);
+        store(A.V, w);
+    }
+}
+
+// ------------------------------------------------------ strided (x, y) pass --
+template <typename T>
+struct SOps {
+    const T* g1;     // first diffusion factor; NULL leaves the array untouched
+    const cx<T>* e;  // E4 table: multiply by E4^2 after the first diffusion (NULL: none)
+    const T* g2;     // second diffusion factor after the multiply (NULL: none)
+};
+
+template <typename T>
+struct SArgs {
+    cx<T>* U;
+    cx<T>* V;
+    int64_t S;            // element stride along the lines
+    int64_t slab_stride;  // distance between slabs of columns
+    int ncols;            // contiguous columns per slab
+    int ntiles;           // column tiles per slab
+    SOps<T> opU, opV;
+};
+
+template <int N2, int TC>
+struct LayS {
+    int c;
+    __device__ __forceinline__ int operator()(int k1, int n2) const { return (k1 * N2 + n2) * TC + c; }
+};
+
+template <typename T, int N2>
+struct SShape {
+    // columns per workgroup: at least one 128-byte row segment, at least one wavefront
+    static constexpr int kMinCols = 128 / int(sizeof(cx<T>));
+    static constexpr int kCols = (64 / N2 > kMinCols) ? 64 / N2 : kMinCols;
+    static constexpr int kThreads = kCols * N2;
+};
+
+// AXIS (0 = x, 1 = y) only names the kernel, so profiles tell the passes apart.
+template <typename T, int N1, int N2, int AXIS>
+__global__ __launch_bounds__((SShape<T, N2>::kThreads)) void k_spass(SArgs<T> A)
+{
+    constexpr int TC = SShape<T, N2>::kCols;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int c = tid % TC, t = tid / TC;
+    const int slab = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
+    const int col = tile * TC + c;
+    const bool act = col < A.ncols;
+    const int64_t base = (int64_t)slab * A.slab_stride + col + (int64_t)t * A.S;
+    const int64_t step = (int64_t)N2 * A.S;
+    const LayS<N2, TC> lay{c};
+
+    auto run = [&](cx<T>* X, const SOps<T>& op) {
+        if (!op.g1) return;
+        cx<T> a[N1];
+        if (act) {
+            sfor<0, N1>([&](auto I) { a[decltype(I)::value] = X[base + decltype(I)::value * step]; });
+        } else {
+            sfor<0, N1>([&](auto I) { a[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+        }
+        diffuse<N1, N2>(a, t, sh, lay, op.g1);
+        if (op.e) {
+            if (act) {
+                sfor<0, N1>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const cx<T> e = op.e[base + i * step];
+                    a[i] = a[i] * (e * e);
+                });
+            }
+            if (op.g2) diffuse<N1, N2>(a, t, sh, lay, op.g2);
+        }
+        if (act) sfor<0, N1>([&](auto I) { X[base + decltype(I)::value * step] = a[decltype(I)::value]; });
+    };
+    run(A.U, A.opU);
+    run(A.V, A.opV);
+}
+
+// ------------------------------------------------------------ launchers ----
+// Axis lengths with a kernel, as (N, N1, N2): N1 points per lane, N2 lanes per line.
+#define PFT_AXIS_SIZES(X) \
+    X(8, 8, 1)            \
+    X(12, 12, 1)          \
+    X(16, 16, 1)          \
+    X(20, 20, 1)          \
+    X(24, 12, 2)          \
+    X(32, 16, 2)          \
+    X(40, 20, 2)          \
+    X(48, 12, 4)          \
+    X(64, 16, 4)          \
+    X(80, 20, 4)          \
+    X(96, 24, 4)          \
+    X(128, 16, 8)         \
+    X(192, 24, 8)         \
+    X(256, 16, 16)
+
+inline bool axis_supported(int n)
+{
+    switch (n) {
+#define PFT_CASE(N, N1, N2) case N:
+        PFT_AXIS_SIZES(PFT_CASE)
+#undef PFT_CASE
+        return true;
+    default:
+        return false;
+    }
+}
+
+template <typename T>
+hipError_t launch_zpass(int nz, const ZArgs<T>& a, hipStream_t s);
+
+template <typename T>
+hipError_t launch_spass(int axis, int n, int64_t ncols_total, SArgs<T> a, int nslabs, hipStream_t s);
+
+}  // namespace pft

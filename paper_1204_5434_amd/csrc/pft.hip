@@ -1,0 +1,1053 @@
+// Host runtime and C ABI of the propagator library (see include/pft.h), plus
+// the elementwise and reduction kernels around the axis passes: field
+// operator tables, the contour-weighted q * q-dagger reduction, Q, H, the
+// Euler-Maruyama field step and its Philox4x64-10 noise.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pft.h"
+#include "kernels.h"
+
+using pft::cx;
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ============================================================ device code ==
+
+// Neumaier-compensated double accumulator.
+struct NSum {
+    double s = 0.0, c = 0.0;
+    __device__ __forceinline__ void add(double x)
+    {
+        const double t = s + x;
+        if (fabs(s) >= fabs(x))
+            c += (s - t) + x;
+        else
+            c += (x - t) + s;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return s + c; }
+};
+
+constexpr int kRedThreads = 256;
+
+// Fixed-order tree sum over the block (deterministic).
+__device__ __forceinline__ double2 block_sum(double2 v, double2* sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            sh[tid].x += sh[tid + w].x;
+            sh[tid].y += sh[tid + w].y;
+        }
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b)
+{
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// Field operator tables E = exp(-w_b a) for up to four (block, a) pairs,
+// evaluated in double and rounded once to the working precision.
+struct TabDesc {
+    int n;
+    int blk[4];
+    double a[4];
+};
+
+template <typename T>
+__global__ void k_field_tables(const double2* __restrict__ wp, const double2* __restrict__ wm, int64_t M,
+                               TabDesc d, cx<T>* __restrict__ out)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
+        const double2 p = wp[x], m = wm[x];
+        // w_A = i w_+ - w_-, w_B = i w_+ + w_-
+        const double2 wA = make_double2(-p.y - m.x, p.x - m.y);
+        const double2 wB = make_double2(-p.y + m.x, p.x + m.y);
+        for (int k = 0; k < d.n; ++k) {
+            const double2 w = d.blk[k] == 0 ? wA : wB;
+            const double mag = exp(-w.x * d.a[k]);
+            double s, c;
+            sincos(-w.y * d.a[k], &s, &c);
+            out[(int64_t)k * M + x] = cx<T>{T(mag * c), T(mag * s)};
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_to_work(const double2* __restrict__ in, cx<T>* __restrict__ out, int64_t M)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x)
+        out[x] = cx<T>{T(in[x].x), T(in[x].y)};
+}
+
+template <typename T>
+__global__ void k_from_work(const cx<T>* __restrict__ in, double2* __restrict__ out, int64_t M)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x)
+        out[x] = make_double2(double(in[x].re), double(in[x].im));
+}
+
+// Partial sums (one per block) of a complex array, compensated.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_sum_partials(const cx<T>* __restrict__ x, int64_t n,
+                                                              double2* __restrict__ partials)
+{
+    __shared__ double2 sh[kRedThreads];
+    NSum re, im;
+    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
+        re.add(double(x[i].re));
+        im.add(double(x[i].im));
+    }
+    const double2 s = block_sum(make_double2(re.value(), im.value()), sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Per-node sums of q_j * qd_{K-j}: blockIdx.y is the node.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_nodeq_partials(const cx<T>* __restrict__ qs,
+                                                                const cx<T>* __restrict__ qds, int K, int64_t M,
+                                                                double2* __restrict__ partials)
+{
+    __shared__ double2 sh[kRedThreads];
+    const int j = blockIdx.y;
+    const cx<T>* a = qs + (int64_t)j * M;
+    const cx<T>* b = qds + (int64_t)(K - j) * M;
+    NSum re, im;
+    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < M; i += (int64_t)gridDim.x * kRedThreads) {
+        const double2 p = cmul(make_double2(a[i].re, a[i].im), make_double2(b[i].re, b[i].im));
+        re.add(p.x);
+        im.add(p.y);
+    }
+    const double2 s = block_sum(make_double2(re.value(), im.value()), sh);
+    if (threadIdx.x == 0) partials[(int64_t)j * gridDim.x + blockIdx.x] = s;
+}
+
+// Final reduction of nrows rows of np partials each: out[r] = scale * sum.
+// Optionally flags a non-finite result (bit 0) and mirrors row 0 to out2.
+__global__ __launch_bounds__(kRedThreads) void k_final_sum(const double2* __restrict__ partials, int np,
+                                                           double scale, double2* __restrict__ out,
+                                                           double2* __restrict__ out2, uint32_t* flags)
+{
+    __shared__ double2 sh[kRedThreads];
+    const int r = blockIdx.x;
+    NSum re, im;
+    for (int i = threadIdx.x; i < np; i += kRedThreads) {
+        re.add(partials[(int64_t)r * np + i].x);
+        im.add(partials[(int64_t)r * np + i].y);
+    }
+    const double2 s = block_sum(make_double2(re.value(), im.value()), sh);
+    if (threadIdx.x == 0) {
+        const double2 v = make_double2(s.x * scale, s.y * scale);
+        out[r] = v;
+        if (out2 && r == 0) *out2 = v;
+        if (flags && !(isfinite(v.x) && isfinite(v.y)) ) atomicOr(flags, 1u);
+    }
+}
+
+// Contour-weighted q * q-dagger reduction (Eq. (8) divided by rho_0):
+// phi_A(x) = (1/Q) sum_{j <= J} tauA_j q_j(x) qd_{K-j}(x), phi_B over j >= J.
+// Per-site compensated double sums; each lane owns one site and streams
+// through the K+1 slices of both stores.
+template <typename T>
+__global__ void k_density(const cx<T>* __restrict__ qs, const cx<T>* __restrict__ qds, int K, int J, int64_t M,
+                          const double* __restrict__ tau, const double2* __restrict__ Qp,
+                          double2* __restrict__ phiA, double2* __restrict__ phiB, double2* __restrict__ Qout)
+{
+    const double2 Q = *Qp;
+    if (Qout && blockIdx.x == 0 && threadIdx.x == 0) *Qout = Q;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
+        NSum ar, ai, br, bi;
+        for (int j = 0; j <= K; ++j) {
+            const cx<T> a = qs[(int64_t)j * M + x];
+            const cx<T> b = qds[(int64_t)(K - j) * M + x];
+            const double2 p = cmul(make_double2(a.re, a.im), make_double2(b.re, b.im));
+            if (j <= J) {
+                const double w = tau[j];
+                ar.add(w * p.x);
+                ai.add(w * p.y);
+            }
+            if (j >= J) {
+                const double w = tau[K + 1 + j];
+                br.add(w * p.x);
+                bi.add(w * p.y);
+            }
+        }
+        phiA[x] = cdiv(make_double2(ar.value(), ai.value()), Q);
+        phiB[x] = cdiv(make_double2(br.value(), bi.value()), Q);
+    }
+}
+
+// Partial sums of w_-^2 / chiN - i w_+ (the local part of Eq. (3)).
+__global__ __launch_bounds__(kRedThreads) void k_ham_partials(const double2* __restrict__ wp,
+                                                              const double2* __restrict__ wm, int64_t M,
+                                                              double inv_chiN, double2* __restrict__ partials)
+{
+    __shared__ double2 sh[kRedThreads];
+    NSum re, im;
+    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < M; i += (int64_t)gridDim.x * kRedThreads) {
+        const double2 m = wm[i], p = wp[i];
+        const double2 m2 = cmul(m, m);
+        re.add(m2.x * inv_chiN + p.y);
+        im.add(m2.y * inv_chiN - p.x);
+    }
+    const double2 s = block_sum(make_double2(re.value(), im.value()), sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// H = C dV S - C V Log Q (principal branch), h = H / (C V).
+__global__ __launch_bounds__(kRedThreads) void k_ham_final(const double2* __restrict__ partials, int np, double C,
+                                                           double dV, double V, const double2* __restrict__ Qp,
+                                                           double2* __restrict__ H, double2* __restrict__ hint)
+{
+    __shared__ double2 sh[kRedThreads];
+    NSum re, im;
+    for (int i = threadIdx.x; i < np; i += kRedThreads) {
+        re.add(partials[i].x);
+        im.add(partials[i].y);
+    }
+    const double2 s = block_sum(make_double2(re.value(), im.value()), sh);
+    if (threadIdx.x == 0) {
+        const double2 Q = *Qp;
+        const double lr = 0.5 * log(Q.x * Q.x + Q.y * Q.y);
+        const double li = atan2(Q.y, Q.x);
+        const double2 h = make_double2(C * dV * s.x - C * V * lr, C * dV * s.y - C * V * li);
+        *H = h;
+        if (hint) *hint = make_double2(h.x / (C * V), h.y / (C * V));
+    }
+}
+
+// ------------------------------------------------------------ Philox noise --
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64 -> 128-bit products with a Weyl-sequence key schedule.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        const uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        const uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// Four standard normals for sites 4g..4g+3 of one field: counter (g, field,
+// step, 0), key (seed, replica); Box-Muller on (u0,u1) and (u2,u3), with
+// u = ((bits >> 11) + 1/2) 2^-53 never zero.
+__device__ __forceinline__ void normals4(uint64_t g, int field, uint64_t step, uint64_t seed, uint64_t rep,
+                                         double z[4])
+{
+    uint64_t c[4] = {g, (uint64_t)field, step, 0};
+    philox4x64_10(c, seed, rep);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const double a = ((double)(c[2 * p] >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double b = ((double)(c[2 * p + 1] >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        const double rad = sqrt(-2.0 * log(a));
+        double s, co;
+        sincos(kTwoPi * b, &s, &co);
+        z[2 * p] = rad * co;
+        z[2 * p + 1] = rad * s;
+    }
+}
+
+__global__ void k_noise_words(uint64_t seed, uint64_t rep, uint64_t step, int field, int64_t ngroups,
+                              uint64_t* __restrict__ out)
+{
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ngroups; g += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t c[4] = {(uint64_t)g, (uint64_t)field, step, 0};
+        philox4x64_10(c, seed, rep);
+        for (int r = 0; r < 4; ++r) out[4 * g + r] = c[r];
+    }
+}
+
+__global__ void k_noise_normals(uint64_t seed, uint64_t rep, uint64_t step, int field, int64_t M,
+                                double* __restrict__ out)
+{
+    const int64_t ng = (M + 3) / 4;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (int64_t)gridDim.x * blockDim.x) {
+        double z[4];
+        normals4(g, field, step, seed, rep, z);
+        for (int r = 0; r < 4 && 4 * g + r < M; ++r) out[4 * g + r] = z[r];
+    }
+}
+
+// Explicit Euler-Maruyama field step, Eq. (9), in place, one lane per block
+// of four sites: F_+ = i (phi_A + phi_B - 1), F_- = 2 w_-/chiN + phi_B - phi_A.
+struct UpdArgs {
+    double2* wp;
+    double2* wm;
+    const double2* phiA;
+    const double2* phiB;
+    int64_t M;
+    double two_over_chiN, dtp, dtm, sp, sm;
+    int noise;
+    uint64_t seed, rep, step;
+};
+
+__global__ void k_update(UpdArgs a)
+{
+    const int64_t ng = (a.M + 3) / 4;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (int64_t)gridDim.x * blockDim.x) {
+        double zp[4] = {0, 0, 0, 0}, zm[4] = {0, 0, 0, 0};
+        if (a.noise) {
+            normals4(g, 0, a.step, a.seed, a.rep, zp);
+            normals4(g, 1, a.step, a.seed, a.rep, zm);
+        }
+        for (int r = 0; r < 4; ++r) {
+            const int64_t x = 4 * g + r;
+            if (x >= a.M) break;
+            const double2 pa = a.phiA[x], pb = a.phiB[x], p = a.wp[x], m = a.wm[x];
+            // F_+ = i (phi - 1)
+            const double2 Fp = make_double2(-(pa.y + pb.y), pa.x + pb.x - 1.0);
+            const double2 Fm = make_double2(a.two_over_chiN * m.x + pb.x - pa.x, a.two_over_chiN * m.y + pb.y - pa.y);
+            a.wp[x] = make_double2(p.x - a.dtp * Fp.x + a.sp * zp[r], p.y - a.dtp * Fp.y);
+            a.wm[x] = make_double2(m.x - a.dtm * Fm.x + a.sm * zm[r], m.y - a.dtm * Fm.y);
+        }
+    }
+}
+
+// ============================================================== host side ==
+
+int grid_for(int64_t n, int threads, int cap = 8192)
+{
+    const int64_t b = (n + threads - 1) / threads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+int reduction_blocks(int64_t n) { return grid_for(n, kRedThreads * 8, 1024); }
+
+// Contour plan; see pft_contour_plan in the header.
+int contour_plan(int ns, double f, double* h, int* blk, int* junction)
+{
+    if (ns < 2 || !(f > 0.0 && f < 1.0)) return -1;
+    const double ds = 1.0 / ns;
+    const double fn = f * ns;
+    const double r = std::floor(fn + 0.5);
+    int K = 0;
+    if (std::fabs(fn - r) <= 1e-9) {
+        const int na = (int)r;
+        for (int j = 0; j < ns; ++j) {
+            h[K] = ds;
+            blk[K] = j < na ? 0 : 1;
+            ++K;
+        }
+        *junction = na;
+    } else {
+        const int nst = (int)std::floor(fn);
+        for (int j = 0; j < nst; ++j) {
+            h[K] = ds;
+            blk[K++] = 0;
+        }
+        h[K] = f - nst * ds;
+        blk[K++] = 0;
+        h[K] = (nst + 1) * ds - f;
+        blk[K++] = 1;
+        for (int j = nst + 1; j < ns; ++j) {
+            h[K] = ds;
+            blk[K++] = 1;
+        }
+        *junction = nst + 1;
+    }
+    return K;
+}
+
+}  // namespace
+
+struct pft_ctx {
+    pft_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int64_t M = 0;
+    int K = 0, J = 0;
+    std::vector<double> h;
+    std::vector<int> blk, kind, hid;  // per step: E table kind (0..3), step-length id (0..2)
+    double hval[3] = {0, 0, 0};       // ds, A junction sub-step, B junction sub-step
+    int maxN = 0;
+    size_t elem = 0;                  // bytes per propagator value
+    // device buffers
+    void* qs = nullptr;
+    void* qds = nullptr;
+    void* U = nullptr;
+    void* V = nullptr;
+    void* E = nullptr;     // 4 * M field operator tables
+    void* work = nullptr;  // 2 * M scratch in working precision
+    void* gtab = nullptr;  // diffusion factors: [hid 3][half/full 2][axis 3][maxN]
+    double* tau = nullptr; // 2 (K+1) trapezoid weights
+    double2* phi = nullptr;       // internal phi_A, phi_B (2 M)
+    double2* partials = nullptr;  // reduction scratch
+    double2* scal = nullptr;      // [0] Q, [1] H, [2] h, [3..] node Q
+    uint32_t* flags = nullptr;
+    int nparts = 0;
+    bool propagated = false;
+    std::string err;
+    // profiling: event pairs recorded around each launch while prof is set
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    std::vector<int> ev_kind;
+    std::vector<double> ev_bytes;
+
+    pft_status fail(pft_status s, const char* fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return s;
+    }
+};
+
+namespace {
+
+#define PFT_HIP(ctx, call)                                                                             \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return (ctx)->fail(PFT_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));           \
+    } while (0)
+
+bool aligned16(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Brackets one launch with a pair of events on the context stream while
+// profiling is on; records the launch's kernel kind and algorithmic bytes.
+struct ProfScope {
+    pft_ctx* c;
+    size_t i = 0;
+    bool on;
+    ProfScope(pft_ctx* ctx, int kind, double bytes) : c(ctx), on(ctx->prof)
+    {
+        if (!on) return;
+        i = c->ev_used;
+        while (c->ev.size() < 2 * (i + 1)) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return;
+            }
+            c->ev.push_back(e);
+        }
+        if (c->ev_kind.size() <= i) {
+            c->ev_kind.resize(i + 1);
+            c->ev_bytes.resize(i + 1);
+        }
+        c->ev_kind[i] = kind;
+        c->ev_bytes[i] = bytes;
+        c->ev_used = i + 1;
+        (void)hipEventRecord(c->ev[2 * i], c->stream);
+    }
+    ~ProfScope()
+    {
+        if (on) (void)hipEventRecord(c->ev[2 * i + 1], c->stream);
+    }
+};
+
+template <typename T>
+const T* gptr(const pft_ctx* c, int hid, int full, int axis)
+{
+    return static_cast<const T*>(c->gtab) + ((size_t)((hid * 2 + full) * 3 + axis)) * c->maxN;
+}
+
+template <typename T>
+cx<T>* etab(const pft_ctx* c, int kind)
+{
+    return static_cast<cx<T>*>(c->E) + (size_t)kind * c->M;
+}
+
+template <typename T>
+cx<T>* slice(void* store, const pft_ctx* c, int node)
+{
+    return static_cast<cx<T>*>(store) + (size_t)node * c->M;
+}
+
+// Z pass completing step `prev` (-1: none) and starting step `next` (-1: none).
+template <typename T>
+pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout)
+{
+    pft::ZArgs<T> a{};
+    a.nlines = (int64_t)c->p.nx * c->p.ny;
+    a.U = static_cast<cx<T>*>(c->U);
+    a.V = static_cast<cx<T>*>(c->V);
+    a.qin = qin;
+    a.qout = qout;
+    a.scheme = c->p.scheme;
+    a.has_prev = prev >= 0;
+    a.has_next = next >= 0;
+    if (prev >= 0) {
+        a.Ep = etab<T>(c, c->kind[prev]);
+        a.gh_p = gptr<T>(c, c->hid[prev], 0, 2);
+    }
+    if (next >= 0) {
+        a.En = etab<T>(c, c->kind[next]);
+        a.gh_n = gptr<T>(c, c->hid[next], 0, 2);
+        a.gf_n = gptr<T>(c, c->hid[next], 1, 2);
+    }
+    // algorithmic bytes: each distinct array read or written once
+    const double E = (double)c->elem * (double)c->M;
+    const bool rqm4 = c->p.scheme == PFT_RQM4;
+    double bytes = 0;
+    if (prev >= 0) bytes += (rqm4 ? 3 : 2) * E;
+    else if (qin) bytes += E;
+    if (qout) bytes += E;
+    if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
+    ProfScope ps(c, PFT_K_ZPASS, bytes);
+    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, a, c->stream));
+    return PFT_OK;
+}
+
+// Strided pass along axis 0 (x) or 1 (y).
+template <typename T>
+pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV)
+{
+    pft::SArgs<T> a{};
+    a.U = static_cast<cx<T>*>(c->U);
+    a.V = static_cast<cx<T>*>(c->V);
+    a.opU = opU;
+    a.opV = opV;
+    const double E = (double)c->elem * (double)c->M;
+    double bytes = (opU.g1 ? 2 * E : 0) + (opV.g1 ? 2 * E : 0);
+    if (opU.g1 && opU.e) bytes += E;
+    if (opV.g1 && opV.e && !(opU.g1 && opU.e == opV.e)) bytes += E;
+    ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes);
+    const int64_t nynz = (int64_t)c->p.ny * c->p.nz;
+    if (axis == 0) {
+        a.S = nynz;
+        a.slab_stride = 0;
+        PFT_HIP(c, pft::launch_spass<T>(0, c->p.nx, nynz, a, 1, c->stream));
+    } else {
+        a.S = c->p.nz;
+        a.slab_stride = nynz;
+        PFT_HIP(c, pft::launch_spass<T>(1, c->p.ny, c->p.nz, a, c->p.nx, c->stream));
+    }
+    return PFT_OK;
+}
+
+// The Y1, X, Y2 passes of step j (Y, X for the plain split).
+template <typename T>
+pft_status step_body(pft_ctx* c, int j)
+{
+    const int hd = c->hid[j];
+    const cx<T>* e = etab<T>(c, c->kind[j]);
+    const pft::SOps<T> none{nullptr, nullptr, nullptr};
+    pft_status s;
+    if (c->p.scheme == PFT_RQM4) {
+        s = spass<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, {gptr<T>(c, hd, 1, 1), nullptr, nullptr});
+        if (s) return s;
+        s = spass<T>(c, 0, {gptr<T>(c, hd, 0, 0), e, gptr<T>(c, hd, 0, 0)}, {gptr<T>(c, hd, 1, 0), e, nullptr});
+        if (s) return s;
+        return spass<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, none);
+    }
+    s = spass<T>(c, 1, none, {gptr<T>(c, hd, 1, 1), nullptr, nullptr});
+    if (s) return s;
+    return spass<T>(c, 0, none, {gptr<T>(c, hd, 1, 0), nullptr, nullptr});
+}
+
+// One sweep over the K steps, forward (q) or mirrored (q-dagger), storing
+// every node into `store`.
+template <typename T>
+pft_status sweep(pft_ctx* c, bool backward, void* store)
+{
+    auto stepj = [&](int i) { return backward ? c->K - 1 - i : i; };
+    pft_status s = zpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0));
+    if (s) return s;
+    for (int i = 0; i < c->K; ++i) {
+        const int j = stepj(i);
+        s = step_body<T>(c, j);
+        if (s) return s;
+        s = zpass<T>(c, j, i + 1 < c->K ? stepj(i + 1) : -1, nullptr, slice<T>(store, c, i + 1));
+        if (s) return s;
+    }
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
+{
+    TabDesc d{};
+    d.n = 4;
+    d.blk[0] = 0; d.a[0] = c->hval[0] / 4;
+    d.blk[1] = 1; d.a[1] = c->hval[0] / 4;
+    d.blk[2] = 0; d.a[2] = c->hval[1] / 4;
+    d.blk[3] = 1; d.a[3] = c->hval[2] / 4;
+    if (c->K == c->p.ns) d.n = 2;  // no junction sub-steps
+    {
+        ProfScope ps(c, PFT_K_TABLES, (32.0 + d.n * (double)c->elem) * (double)c->M);
+        hipLaunchKernelGGL((k_field_tables<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<const double2*>(wp), reinterpret_cast<const double2*>(wm), c->M, d,
+                       static_cast<cx<T>*>(c->E));
+    }
+    PFT_HIP(c, hipGetLastError());
+    pft_status s = sweep<T>(c, false, c->qs);
+    if (s) return s;
+    s = sweep<T>(c, true, c->qds);
+    if (s) return s;
+    // Q = (1/M) sum_x q_K(x)
+    ProfScope ps(c, PFT_K_REDUCE, (double)c->elem * (double)c->M);
+    hipLaunchKernelGGL((k_sum_partials<T>), dim3(c->nparts), dim3(kRedThreads), 0, c->stream,
+                       slice<T>(c->qs, c, c->K), c->M, c->partials);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, c->nparts,
+                       1.0 / (double)c->M, c->scal, (double2*)nullptr, c->flags);
+    PFT_HIP(c, hipGetLastError());
+    c->propagated = true;
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status densities_t(pft_ctx* c, double* phi_a, double* phi_b, double* Q)
+{
+    ProfScope ps(c, PFT_K_DENSITY, (2.0 * (c->K + 1) * (double)c->elem + 2.0 * sizeof(double2)) * (double)c->M);
+    hipLaunchKernelGGL((k_density<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
+                       static_cast<const cx<T>*>(c->qs), static_cast<const cx<T>*>(c->qds), c->K, c->J, c->M,
+                       c->tau, c->scal, reinterpret_cast<double2*>(phi_a), reinterpret_cast<double2*>(phi_b),
+                       reinterpret_cast<double2*>(Q));
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status nodeq_t(pft_ctx* c, double* out)
+{
+    const int nb = std::min(c->nparts, 64);
+    dim3 grid(nb, c->K + 1);
+    hipLaunchKernelGGL((k_nodeq_partials<T>), grid, dim3(kRedThreads), 0, c->stream, static_cast<const cx<T>*>(c->qs),
+                       static_cast<const cx<T>*>(c->qds), c->K, c->M, c->partials);
+    hipLaunchKernelGGL(k_final_sum, dim3(c->K + 1), dim3(kRedThreads), 0, c->stream, c->partials, nb,
+                       1.0 / (double)c->M, reinterpret_cast<double2*>(out), (double2*)nullptr, (uint32_t*)nullptr);
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status get_slice_t(pft_ctx* c, int which, int node, double* out)
+{
+    const cx<T>* src = slice<T>(which ? c->qds : c->qs, c, node);
+    hipLaunchKernelGGL((k_from_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream, src,
+                       reinterpret_cast<double2*>(out), c->M);
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status apply_step_t(pft_ctx* c, int j, const double* qin, double* qout)
+{
+    cx<T>* w0 = static_cast<cx<T>*>(c->work);
+    cx<T>* w1 = w0 + c->M;
+    hipLaunchKernelGGL((k_to_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<const double2*>(qin), w0, c->M);
+    PFT_HIP(c, hipGetLastError());
+    pft_status s = zpass<T>(c, -1, j, w0, nullptr);
+    if (s) return s;
+    s = step_body<T>(c, j);
+    if (s) return s;
+    s = zpass<T>(c, j, -1, nullptr, w1);
+    if (s) return s;
+    hipLaunchKernelGGL((k_from_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream, w1,
+                       reinterpret_cast<double2*>(qout), c->M);
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+template <typename T>
+std::vector<T> axis_factors(int n, double L, double h)
+{
+    std::vector<T> g(n);
+    for (int j = 0; j < n; ++j) {
+        const int m = (j <= n / 2) ? j : j - n;
+        const double k = kTwoPi * m / L;
+        g[j] = T(std::exp(-k * k * h) / n);
+    }
+    return g;
+}
+
+template <typename T>
+pft_status upload_factors(pft_ctx* c, int hid, double h)
+{
+    const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
+    for (int full = 0; full < 2; ++full)
+        for (int ax = 0; ax < 3; ++ax) {
+            const std::vector<T> g = axis_factors<T>(n[ax], L[ax], full ? h : h / 2);
+            PFT_HIP(c, hipMemcpy(const_cast<T*>(gptr<T>(c, hid, full, ax)), g.data(), g.size() * sizeof(T),
+                                 hipMemcpyHostToDevice));
+        }
+    return PFT_OK;
+}
+
+// D_h through the axis passes: u is staged in the working precision, run
+// through the z, y and x passes with the full-step factors for h (kept in a
+// spare table slot so the step tables stay intact) and read back from V.
+// The work arrays are overwritten; the propagator stores are not touched.
+template <typename T>
+pft_status diffuse_t(pft_ctx* c, double* u, double h)
+{
+    PFT_HIP(c, hipStreamSynchronize(c->stream));  // earlier work may still read the spare slot
+    pft_status s = upload_factors<T>(c, 3, h);
+    if (s) return s;
+    cx<T>* w0 = static_cast<cx<T>*>(c->work);
+    hipLaunchKernelGGL((k_to_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<const double2*>(u), w0, c->M);
+    PFT_HIP(c, hipGetLastError());
+    pft::ZArgs<T> a{};
+    a.nlines = (int64_t)c->p.nx * c->p.ny;
+    a.U = static_cast<cx<T>*>(c->U);
+    a.V = static_cast<cx<T>*>(c->V);
+    a.qin = w0;
+    a.scheme = PFT_SPLIT2;
+    a.has_next = 1;
+    a.gh_n = gptr<T>(c, 3, 0, 2);
+    a.gf_n = gptr<T>(c, 3, 1, 2);
+    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, a, c->stream));
+    const pft::SOps<T> none{nullptr, nullptr, nullptr};
+    s = spass<T>(c, 1, none, {gptr<T>(c, 3, 1, 1), nullptr, nullptr});
+    if (s) return s;
+    s = spass<T>(c, 0, none, {gptr<T>(c, 3, 1, 0), nullptr, nullptr});
+    if (s) return s;
+    hipLaunchKernelGGL((k_from_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
+                       static_cast<const cx<T>*>(c->V), reinterpret_cast<double2*>(u), c->M);
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+void free_all(pft_ctx* c)
+{
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    c->ev.clear();
+    void* bufs[] = {c->qs, c->qds, c->U, c->V, c->E, c->work, c->gtab, c->tau, c->phi, c->partials, c->scal, c->flags};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+}
+
+}  // namespace
+
+// ================================================================ C ABI ====
+extern "C" {
+
+const char* pft_status_string(pft_status s)
+{
+    switch (s) {
+    case PFT_OK: return "PFT_OK";
+    case PFT_E_INVALID: return "PFT_E_INVALID";
+    case PFT_E_UNSUPPORTED: return "PFT_E_UNSUPPORTED";
+    case PFT_E_NOMEM: return "PFT_E_NOMEM";
+    case PFT_E_DEVICE: return "PFT_E_DEVICE";
+    case PFT_E_NONFINITE: return "PFT_E_NONFINITE";
+    case PFT_E_STATE: return "PFT_E_STATE";
+    }
+    return "PFT_E_UNKNOWN";
+}
+
+int32_t pft_contour_plan(int32_t ns, double f, double* h, int32_t* blk, int32_t* junction)
+{
+    if (!h || !blk || !junction) return -1;
+    std::vector<int> b(ns > 0 ? ns + 1 : 1);
+    int J = 0;
+    const int K = contour_plan(ns, f, h, b.data(), &J);
+    if (K < 0) return -1;
+    for (int j = 0; j < K; ++j) blk[j] = b[j];
+    *junction = J;
+    return K;
+}
+
+pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
+{
+    if (!out) return PFT_E_INVALID;
+    *out = nullptr;
+    if (!params) return PFT_E_INVALID;
+    const pft_params& p = *params;
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1 || !(p.lx > 0) || !(p.ly > 0) || !(p.lz > 0) || p.ns < 2 ||
+        !(p.f > 0.0 && p.f < 1.0) || !(p.chiN > 0) || !(p.C > 0) || (p.precision != PFT_C128 && p.precision != PFT_C64) ||
+        (p.scheme != PFT_RQM4 && p.scheme != PFT_SPLIT2))
+        return PFT_E_INVALID;
+    if (!pft::axis_supported(p.nx) || !pft::axis_supported(p.ny) || !pft::axis_supported(p.nz))
+        return PFT_E_UNSUPPORTED;
+
+    pft_ctx* c = new (std::nothrow) pft_ctx();
+    if (!c) return PFT_E_NOMEM;
+    c->p = p;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->M = (int64_t)p.nx * p.ny * p.nz;
+    c->maxN = std::max(p.nx, std::max(p.ny, p.nz));
+    c->elem = p.precision == PFT_C128 ? sizeof(cx<double>) : sizeof(cx<float>);
+    c->h.resize(p.ns + 1);
+    c->blk.resize(p.ns + 1);
+    c->K = contour_plan(p.ns, p.f, c->h.data(), c->blk.data(), &c->J);
+    const double ds = 1.0 / p.ns;
+    c->hval[0] = ds;
+    c->kind.resize(c->K);
+    c->hid.resize(c->K);
+    for (int j = 0; j < c->K; ++j) {
+        const bool regular = (c->K == p.ns) || !(j == c->J - 1 || j == c->J);
+        if (regular) {
+            c->kind[j] = c->blk[j];
+            c->hid[j] = 0;
+        } else {
+            c->kind[j] = 2 + c->blk[j];
+            c->hid[j] = 1 + c->blk[j];
+            c->hval[1 + c->blk[j]] = c->h[j];
+        }
+    }
+    // trapezoid weights per block: tau[0..K] for A, tau[K+1..2K+1] for B
+    std::vector<double> tau(2 * (c->K + 1), 0.0);
+    for (int j = 0; j < c->K; ++j) {
+        double* t = tau.data() + (c->blk[j] == 0 ? 0 : c->K + 1);
+        t[j] += 0.5 * c->h[j];
+        t[j + 1] += 0.5 * c->h[j];
+    }
+    c->nparts = reduction_blocks(c->M);
+
+    auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess; };
+    const size_t store = (size_t)(c->K + 1) * c->M * c->elem;
+    bool ok = alloc(&c->qs, store) && alloc(&c->qds, store) && alloc(&c->U, c->M * c->elem) &&
+              alloc(&c->V, c->M * c->elem) && alloc(&c->E, 4 * c->M * c->elem) && alloc(&c->work, 2 * c->M * c->elem) &&
+              alloc(&c->gtab, (size_t)4 * 2 * 3 * c->maxN * (c->elem / 2)) &&
+              alloc((void**)&c->tau, tau.size() * sizeof(double)) && alloc((void**)&c->phi, 2 * c->M * sizeof(double2)) &&
+              alloc((void**)&c->partials, (size_t)std::max(c->nparts, 64 * (c->K + 1)) * sizeof(double2)) &&
+              alloc((void**)&c->scal, (size_t)(8 + c->K + 1) * sizeof(double2)) && alloc((void**)&c->flags, sizeof(uint32_t));
+    if (!ok) {
+        (void)hipGetLastError();
+        free_all(c);
+        delete c;
+        return PFT_E_NOMEM;
+    }
+    pft_status s = PFT_OK;
+    if (hipMemcpy(c->tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(c->flags, 0, sizeof(uint32_t)) != hipSuccess || hipMemset(c->scal, 0, (8 + c->K + 1) * sizeof(double2)) != hipSuccess)
+        s = PFT_E_DEVICE;
+    for (int hd = 0; hd < 3 && s == PFT_OK; ++hd) {
+        const double hv = c->hval[hd] > 0 ? c->hval[hd] : ds;
+        s = p.precision == PFT_C128 ? upload_factors<double>(c, hd, hv) : upload_factors<float>(c, hd, hv);
+    }
+    if (s != PFT_OK) {
+        free_all(c);
+        delete c;
+        return s;
+    }
+    *out = c;
+    return PFT_OK;
+}
+
+void pft_destroy(pft_ctx* c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+const char* pft_last_error(const pft_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int32_t pft_num_steps(const pft_ctx* c) { return c ? c->K : -1; }
+
+pft_status pft_propagate(pft_ctx* c, const double* wp, const double* wm)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(wp) || !aligned16(wm)) return c->fail(PFT_E_INVALID, "w_plus/w_minus must be non-null and 16-byte aligned");
+    c->propagated = false;
+    return c->p.precision == PFT_C128 ? propagate_t<double>(c, wp, wm) : propagate_t<float>(c, wp, wm);
+}
+
+pft_status pft_densities(pft_ctx* c, double* phi_a, double* phi_b, double* Q)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(phi_a) || !aligned16(phi_b) || (Q && !aligned16(Q)))
+        return c->fail(PFT_E_INVALID, "phi_a/phi_b must be non-null and 16-byte aligned (Q aligned if given)");
+    if (!c->propagated) return c->fail(PFT_E_STATE, "pft_densities needs a prior pft_propagate");
+    return c->p.precision == PFT_C128 ? densities_t<double>(c, phi_a, phi_b, Q) : densities_t<float>(c, phi_a, phi_b, Q);
+}
+
+pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, double* H, double* hint)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(wp) || !aligned16(wm) || !aligned16(H) || (hint && !aligned16(hint)))
+        return c->fail(PFT_E_INVALID, "w_plus/w_minus/H must be non-null and 16-byte aligned");
+    if (!c->propagated) return c->fail(PFT_E_STATE, "pft_hamiltonian needs a prior pft_propagate");
+    const double V = c->p.lx * c->p.ly * c->p.lz;
+    ProfScope ps(c, PFT_K_REDUCE, 2.0 * sizeof(double2) * (double)c->M);
+    hipLaunchKernelGGL(k_ham_partials, dim3(c->nparts), dim3(kRedThreads), 0, c->stream,
+                       reinterpret_cast<const double2*>(wp), reinterpret_cast<const double2*>(wm), c->M,
+                       1.0 / c->p.chiN, c->partials);
+    hipLaunchKernelGGL(k_ham_final, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, c->nparts, c->p.C,
+                       V / (double)c->M, V, c->scal, reinterpret_cast<double2*>(H), reinterpret_cast<double2*>(hint));
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, double* phi_a, double* phi_b,
+                       double* Q, double* H)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!st) return c->fail(PFT_E_INVALID, "step parameters are NULL");
+    if (!(st->dt >= 0) || !(st->lambda_plus >= 0) || !(st->lambda_minus >= 0))
+        return c->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
+    if ((phi_a && !aligned16(phi_a)) || (phi_b && !aligned16(phi_b)) || (Q && !aligned16(Q)) || (H && !aligned16(H)))
+        return c->fail(PFT_E_INVALID, "optional outputs must be 16-byte aligned");
+    double* pa = phi_a ? phi_a : reinterpret_cast<double*>(c->phi);
+    double* pb = phi_b ? phi_b : reinterpret_cast<double*>(c->phi + c->M);
+    pft_status s = pft_propagate(c, wp, wm);
+    if (s) return s;
+    s = pft_densities(c, pa, pb, Q);
+    if (s) return s;
+    s = pft_hamiltonian(c, wp, wm, H ? H : reinterpret_cast<double*>(c->scal + 1), nullptr);
+    if (s) return s;
+    const double dV = c->p.lx * c->p.ly * c->p.lz / (double)c->M;
+    UpdArgs a{};
+    a.wp = reinterpret_cast<double2*>(wp);
+    a.wm = reinterpret_cast<double2*>(wm);
+    a.phiA = reinterpret_cast<const double2*>(pa);
+    a.phiB = reinterpret_cast<const double2*>(pb);
+    a.M = c->M;
+    a.two_over_chiN = 2.0 / c->p.chiN;
+    a.dtp = st->lambda_plus * st->dt;
+    a.dtm = st->lambda_minus * st->dt;
+    a.noise = st->noise != 0;
+    a.sp = a.noise ? std::sqrt(2.0 * st->lambda_plus * st->dt / (c->p.C * dV)) : 0.0;
+    a.sm = a.noise ? std::sqrt(2.0 * st->lambda_minus * st->dt / (c->p.C * dV)) : 0.0;
+    a.seed = st->seed;
+    a.rep = st->replica;
+    a.step = st->step;
+    ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
+    hipLaunchKernelGGL(k_update, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+pft_status pft_node_q(pft_ctx* c, double* qnode)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(qnode)) return c->fail(PFT_E_INVALID, "qnode must be non-null and 16-byte aligned");
+    if (!c->propagated) return c->fail(PFT_E_STATE, "pft_node_q needs a prior pft_propagate");
+    return c->p.precision == PFT_C128 ? nodeq_t<double>(c, qnode) : nodeq_t<float>(c, qnode);
+}
+
+pft_status pft_get_slice(pft_ctx* c, int32_t which, int32_t node, double* out)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(out) || (which != 0 && which != 1) || node < 0 || node > c->K)
+        return c->fail(PFT_E_INVALID, "bad slice request (which %d, node %d of %d)", which, node, c->K);
+    if (!c->propagated) return c->fail(PFT_E_STATE, "pft_get_slice needs a prior pft_propagate");
+    return c->p.precision == PFT_C128 ? get_slice_t<double>(c, which, node, out) : get_slice_t<float>(c, which, node, out);
+}
+
+pft_status pft_apply_step(pft_ctx* c, int32_t j, const double* qin, double* qout)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(qin) || !aligned16(qout) || j < 0 || j >= c->K)
+        return c->fail(PFT_E_INVALID, "bad step request (step %d of %d)", j, c->K);
+    if (!c->propagated) return c->fail(PFT_E_STATE, "pft_apply_step needs the field tables of a prior pft_propagate");
+    return c->p.precision == PFT_C128 ? apply_step_t<double>(c, j, qin, qout) : apply_step_t<float>(c, j, qin, qout);
+}
+
+pft_status pft_diffuse(pft_ctx* c, double* u, double h)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(u) || !(h >= 0)) return c->fail(PFT_E_INVALID, "u must be aligned and h >= 0");
+    return c->p.precision == PFT_C128 ? diffuse_t<double>(c, u, h) : diffuse_t<float>(c, u, h);
+}
+
+pft_status pft_debug_kgrid(const pft_ctx* c, int32_t* m2)
+{
+    if (!c || !m2) return PFT_E_INVALID;
+    const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
+    auto mode = [](int j, int n) { return j <= n / 2 ? j : j - n; };
+    for (int x = 0; x < nx; ++x)
+        for (int y = 0; y < ny; ++y)
+            for (int z = 0; z < nz; ++z) {
+                const int a = mode(x, nx), b = mode(y, ny), d = mode(z, nz);
+                m2[((int64_t)x * ny + y) * nz + z] = a * a + b * b + d * d;
+            }
+    return PFT_OK;
+}
+
+pft_status pft_status_flags(pft_ctx* c, uint32_t* flags)
+{
+    if (!c || !flags) return PFT_E_INVALID;
+    PFT_HIP(c, hipMemcpyAsync(flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    PFT_HIP(c, hipStreamSynchronize(c->stream));
+    return (*flags & 1u) ? PFT_E_NONFINITE : PFT_OK;
+}
+
+pft_status pft_profile_begin(pft_ctx* c)
+{
+    if (!c) return PFT_E_INVALID;
+    c->prof = true;
+    c->ev_used = 0;
+    return PFT_OK;
+}
+
+pft_status pft_profile_end(pft_ctx* c, double* ms, int64_t* launches, double* bytes)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!c->prof) return c->fail(PFT_E_STATE, "pft_profile_end without pft_profile_begin");
+    c->prof = false;
+    PFT_HIP(c, hipStreamSynchronize(c->stream));
+    double m[PFT_K_COUNT] = {}, b[PFT_K_COUNT] = {};
+    int64_t n[PFT_K_COUNT] = {};
+    for (size_t i = 0; i < c->ev_used; ++i) {
+        float t = 0.f;
+        PFT_HIP(c, hipEventElapsedTime(&t, c->ev[2 * i], c->ev[2 * i + 1]));
+        const int k = c->ev_kind[i];
+        m[k] += t;
+        b[k] += c->ev_bytes[i];
+        n[k] += 1;
+    }
+    for (int k = 0; k < PFT_K_COUNT; ++k) {
+        if (ms) ms[k] = m[k];
+        if (launches) launches[k] = n[k];
+        if (bytes) bytes[k] = b[k];
+    }
+    c->ev_used = 0;
+    return PFT_OK;
+}
+
+pft_status pft_noise_words(uint64_t seed, uint64_t rep, uint64_t step, int32_t field, int64_t M, uint64_t* out,
+                           void* stream)
+{
+    if (!out || M < 1 || (field != 0 && field != 1)) return PFT_E_INVALID;
+    const int64_t ng = (M + 3) / 4;
+    hipLaunchKernelGGL(k_noise_words, dim3(grid_for(ng, 256)), dim3(256), 0, static_cast<hipStream_t>(stream), seed, rep,
+                       step, field, ng, out);
+    return hipGetLastError() == hipSuccess ? PFT_OK : PFT_E_DEVICE;
+}
+
+pft_status pft_noise_normals(uint64_t seed, uint64_t rep, uint64_t step, int32_t field, int64_t M, double* out,
+                             void* stream)
+{
+    if (!out || M < 1 || (field != 0 && field != 1)) return PFT_E_INVALID;
+    hipLaunchKernelGGL(k_noise_normals, dim3(grid_for((M + 3) / 4, 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), seed, rep, step, field, M, out);
+    return hipGetLastError() == hipSuccess ? PFT_OK : PFT_E_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+identical seeded inputs.
+
+Bars: complex128 propagators -- |dphi| <= 1e-10, Q and H relative <= 1e-11;
+complex64 propagators (FP64 sums) -- ||dphi||/||phi|| and Q relative <= 2e-5,
+H within 2e-5 (|H| + C V) (the log Q term carries Q's relative error times
+C V); the integer k-grid and the Philox words bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1204_5434_amd import binding as B
+from paper_1204_5434_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rand_fields(shape, seed, sr=0.3, si=0.1):
+    r = np.random.default_rng(seed)
+    wp = sr * r.standard_normal(shape) + 1j * si * r.standard_normal(shape)
+    wm = sr * r.standard_normal(shape) + 1j * si * r.standard_normal(shape)
+    return wp, wm
+
+
+def oparams(orc, n, L, ns, f, chiN, C, scheme):
+    return orc.Params(n[0], n[1], n[2], L[0], L[1], L[2], ns, f, chiN, C, scheme, False)
+
+
+def gparams(n, L, ns, f, chiN, C, scheme, prec):
+    return B.Params(n[0], n[1], n[2], L[0], L[1], L[2], ns, f, chiN, C, prec, scheme)
+
+
+def rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+# ----------------------------------------------------------------- noise --
+
+@pytest.mark.parametrize("M", [1, 5, 4096, 262147])
+def test_noise_words_bit_exact(orc, M):
+    say("noise words M", M)
+    for field in (0, 1):
+        w = host(B.pft_noise_words(1206, 3, 17, field, M)).view(np.uint64)
+        for g in [0, (M - 1) // 4, ((M + 3) // 4) // 2]:
+            ref = orc.philox4x64_10(np.array([g, field, 17, 0], np.uint64), np.array([1206, 3], np.uint64))
+            assert np.array_equal(w[4 * g:4 * g + 4], ref)
+
+
+def test_noise_normals(orc):
+    M = 100003
+    z = host(B.pft_noise_normals(1206, 1, 42, 1, M))
+    ref = orc.gaussian(1206, 1, 42, 1, M)
+    assert np.abs(z - ref).max() < 1e-13
+
+
+# ---------------------------------------------------------------- k-grid --
+
+def test_kgrid_bit_exact(orc):
+    ctx = B.Context(gparams((24, 40, 16), (3.0, 5.0, 2.0), 10, 0.5, 10.0, 1.0, 0, B.PFT_C128))
+    m2 = ctx.pft_debug_kgrid()
+    m = [np.array([orc.mode(j, n) for j in range(n)]) for n in (24, 40, 16)]
+    ref = m[0][:, None, None] ** 2 + m[1][None, :, None] ** 2 + m[2][None, None, :] ** 2
+    assert np.array_equal(m2, ref)
+
+
+# -------------------------------------------------------------- diffusion --
+
+def diffusion_case(orc, n, L, h, prec, seed=0):
+    r = np.random.default_rng(seed)
+    u = r.standard_normal(n) + 1j * r.standard_normal(n)
+    ctx = B.Context(gparams(n, L, 4, 0.5, 10.0, 1.0, 0, prec))
+    t = dev(u)
+    ctx.pft_diffuse(t, h)
+    got = host(t)
+    ref = orc.diffuse(oparams(orc, n, L, 4, 0.5, 10.0, 1.0, 0), h, u)
+    ctx.close()
+    return np.abs(got - ref).max() / np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N", B.SUPPORTED_AXES)
+def test_diffusion_every_axis_length(orc, N):
+    for n in [(N, 8, 12), (8, N, 12), (12, 8, N)]:
+        say("diffuse", n)
+        L = (0.3 * n[0], 0.25 * n[1], 0.2 * n[2])
+        e64 = diffusion_case(orc, n, L, 0.01, B.PFT_C128)
+        assert e64 < 1e-13, (n, e64)
+        e32 = diffusion_case(orc, n, L, 0.01, B.PFT_C64)
+        assert e32 < 2e-6, (n, e32)
+
+
+@pytest.mark.parametrize("prec,tol", [(B.PFT_C128, 1e-14), (B.PFT_C64, 1e-6)])
+def test_single_mode(orc, prec, tol):
+    n, L = (32, 24, 40), (3.0, 2.0, 5.0)
+    m = (3, 2, 5)
+    x, y, z = np.meshgrid(*(np.arange(k) for k in n), indexing="ij")
+    u = np.cos(2 * np.pi * (m[0] * x / n[0] + m[1] * y / n[1] + m[2] * z / n[2])) + 0j
+    k2 = sum((2 * np.pi * m[a] / L[a]) ** 2 for a in range(3))
+    ctx = B.Context(gparams(n, L, 4, 0.5, 10.0, 1.0, 0, prec))
+    t = dev(u)
+    ctx.pft_diffuse(t, 0.021)
+    assert np.abs(host(t) - np.exp(-k2 * 0.021) * u).max() < tol
+
+
+# ---------------------------------------------------- full field evaluation --
+
+CASES = [
+    # n, L, ns, f, chiN, C, scheme
+    ((16, 16, 16), (4.0, 4.0, 4.0), 50, 0.5, 15.0, 1.0, 0),
+    ((24, 32, 40), (3.0, 4.0, 5.0), 25, 0.3, 18.0, 2.0, 0),   # junction inside a step
+    ((8, 12, 20), (2.0, 3.0, 5.0), 13, 0.62, 12.0, 1.0, 1),   # plain split + junction
+    ((48, 16, 24), (6.0, 2.0, 3.0), 20, 0.4, 14.4, 3.0, 0),
+    ((20, 64, 8), (2.5, 8.0, 1.0), 16, 0.5, 14.0, 1.0, 1),
+    ((12, 8, 96), (1.5, 1.0, 12.0), 11, 0.35, 22.0, 5.0, 0),
+    ((128, 8, 8), (16.0, 1.0, 1.0), 10, 0.45, 20.0, 1.0, 0),
+    ((8, 8, 256), (1.0, 1.0, 32.0), 8, 0.5, 20.0, 1.0, 0),
+    ((8, 192, 8), (1.0, 24.0, 1.0), 9, 0.55, 20.0, 1.0, 1),
+]
+
+
+def evaluate_both(orc, case, prec, seed):
+    n, L, ns, f, chiN, C, scheme = case
+    wp, wm = rand_fields(n, seed)
+    ref = orc.evaluate(oparams(orc, n, L, ns, f, chiN, C, scheme), wp, wm)
+    ctx = B.Context(gparams(n, L, ns, f, chiN, C, scheme, prec))
+    out = ctx.evaluate(dev(wp), dev(wm))
+    qn = torch.empty(ctx.K + 1, dtype=torch.complex128, device=DEV)
+    ctx.pft_node_q(qn)
+    got = {k: host(v) for k, v in out.items()}
+    got["Qnode"] = host(qn)
+    flags = ctx.pft_status_flags()
+    ctx.close()
+    return got, ref, flags
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-ns{c[2]}-f{c[3]}-s{c[6]}" for c in CASES])
+def test_evaluation_fp64(orc, case):
+    say("fp64 evaluation", case)
+    got, ref, flags = evaluate_both(orc, case, B.PFT_C128, 11)
+    assert flags == 0
+    assert np.abs(got["phiA"] - ref["phiA"]).max() <= 1e-10
+    assert np.abs(got["phiB"] - ref["phiB"]).max() <= 1e-10
+    assert rel(got["Q"][0], ref["Q"]) <= 1e-11
+    assert rel(got["H"][0], ref["H"]) <= 1e-11
+    assert rel(got["h"][0], ref["h"]) <= 1e-11
+    assert np.abs(got["Qnode"] - ref["Qnode"]).max() <= 1e-11 * abs(ref["Q"])
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-ns{c[2]}-f{c[3]}-s{c[6]}" for c in CASES])
+def test_evaluation_fp32(orc, case):
+    say("fp32 evaluation", case)
+    got, ref, flags = evaluate_both(orc, case, B.PFT_C64, 12)
+    assert flags == 0
+    for k in ("phiA", "phiB"):
+        assert np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max() <= 2e-5, k
+    assert rel(got["Q"][0], ref["Q"]) <= 2e-5
+    # H = C dV sum(...) - C V log Q is a difference of two extensive terms, so
+    # Q's relative error e reaches H as C V e: the bound is 2e-5 on that scale.
+    n, L, C = case[0], case[1], case[5]
+    assert abs(got["H"][0] - ref["H"]) <= 2e-5 * (abs(ref["H"]) + C * L[0] * L[1] * L[2])
+
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_constant_fields_closed_form(prec):
+    # q_j = exp(-integral of w) and phi_A = f exactly for constant fields (any size)
+    n, L, ns, f = (32, 48, 40), (4.0, 6.0, 5.0), 30, 0.37
+    a, b = 0.3 + 0.2j, -0.7 + 0.1j
+    wp = np.full(n, -1j * a)
+    wm = np.full(n, b)
+    ctx = B.Context(gparams(n, L, ns, f, 15.0, 1.0, 0, prec))
+    out = ctx.evaluate(dev(wp), dev(wm))
+    tol = 1e-12 if prec == B.PFT_C128 else 2e-6
+    Q = np.exp(-(f * (a - b) + (1 - f) * (a + b)))
+    assert rel(host(out["Q"])[0], Q) < tol
+    assert np.abs(host(out["phiA"]) - f).max() < tol
+    assert np.abs(host(out["phiB"]) - (1 - f)).max() < tol
+
+
+def test_call_order_errors():
+    ctx = B.Context(gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, 15.0, 1.0, 0, B.PFT_C128))
+    phi = torch.empty((16, 16, 16), dtype=torch.complex128, device=DEV)
+    with pytest.raises(B.PftError) as e:
+        ctx.pft_densities(phi, phi.clone())
+    assert e.value.status == B.PFT_E_STATE
+    with pytest.raises(TypeError):
+        ctx.pft_propagate(phi.to(torch.complex64), phi)
+
+
+# ------------------------------------------------------ field update parity --
+
+def test_scft_relaxation_trajectory(orc):
+    # deterministic relaxation (no noise): every iteration's phi, Q, H
+    w = inputs.SCFT16
+    wp, wm = inputs.fields(w)
+    p_or = oparams(orc, w.n, w.L, w.ns, w.f, w.chiN, w.C, 0)
+    ctx = B.Context(gparams(w.n, w.L, w.ns, w.f, w.chiN, w.C, 0, B.PFT_C128))
+    gwp, gwm = dev(wp), dev(wm)
+    st = B.pft_step(w.dt, 1.0, 1.0, 0, 0, 0, 0)
+    phiA = torch.empty(w.n, dtype=torch.complex128, device=DEV)
+    phiB = torch.empty_like(phiA)
+    Q = torch.empty(1, dtype=torch.complex128, device=DEV)
+    H = torch.empty_like(Q)
+    for it in range(20):
+        ref = orc.evaluate(p_or, wp, wm)
+        ctx.pft_cl_step(gwp, gwm, st, phiA, phiB, Q, H)
+        assert np.abs(host(phiA) - ref["phiA"]).max() <= 1e-10, it
+        assert rel(host(Q)[0], ref["Q"]) <= 1e-11 and rel(host(H)[0], ref["H"]) <= 1e-11, it
+        wp, wm = orc.em_update(p_or, wp, wm, ref["phiA"], ref["phiB"], w.dt)
+        assert np.abs(host(gwp) - wp).max() <= 1e-10 and np.abs(host(gwm) - wm).max() <= 1e-10, it
+
+
+@pytest.mark.parametrize("prec,tol", [(B.PFT_C128, 1e-10), (B.PFT_C64, 2e-5)])
+def test_langevin_step_with_noise(orc, prec, tol):
+    w = inputs.CL64.scaled((32, 32, 32), ns=40)
+    wp, wm = inputs.fields(w)
+    p_or = oparams(orc, w.n, w.L, w.ns, w.f, w.chiN, w.C, 0)
+    ctx = B.Context(gparams(w.n, w.L, w.ns, w.f, w.chiN, w.C, 0, prec))
+    gwp, gwm = dev(wp), dev(wm)
+    for step in range(3):
+        st = B.pft_step(w.dt, 1.0, 1.0, w.seed, 0, step, 1)
+        ref = orc.evaluate(p_or, wp, wm)
+        ctx.pft_cl_step(gwp, gwm, st)
+        wp, wm = orc.em_update(p_or, wp, wm, ref["phiA"], ref["phiB"], w.dt, noise=True,
+                               seed=w.seed, replica=0, step_=step)
+        scale = max(np.abs(wp).max(), np.abs(wm).max())
+        assert np.abs(host(gwp) - wp).max() <= tol * scale, step
+        assert np.abs(host(gwm) - wm).max() <= tol * scale, step
+        if prec == B.PFT_C64:  # continue from a common state so errors do not compound
+            gwp, gwm = dev(wp), dev(wm)
+
+
+# --------------------------------------------- full size, bench configuration --
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_full_size_lam128_sampled(orc, prec):
+    """The benchmark workload (128^3, Ns = 100) in the benchmark's launch
+    configuration: sampled one-step parity from the GPU's own stored slices,
+    sampled per-site densities, and the exact invariants at full size."""
+    w = inputs.LAM128
+    say("full size", w.name, "precision", prec)
+    wp, wm = inputs.fields(w)
+    ctx = B.Context(gparams(w.n, w.L, w.ns, w.f, w.chiN, w.C, 0, prec))
+    out = ctx.evaluate(dev(wp), dev(wm))
+    K = ctx.K
+    tol = 1e-12 if prec == B.PFT_C128 else 2e-5
+    p_or = oparams(orc, w.n, w.L, w.ns, w.f, w.chiN, w.C, 0)
+    wA, wB = orc.block_fields(p_or, wp, wm)
+    h, blk, J = orc.contour(w.ns, w.f)
+    qj = torch.empty(w.n, dtype=torch.complex128, device=DEV)
+    qj1 = torch.empty_like(qj)
+    for which, j in ((0, 0), (0, K // 2), (1, K - 1)):
+        say("  one-step check", which, j)
+        ctx.pft_get_slice(which, j, qj)
+        ctx.pft_get_slice(which, j + 1, qj1)
+        step_index = j if which == 0 else K - 1 - j
+        field = wA if blk[step_index] == 0 else wB
+        ref = orc.step(p_or, h[step_index], field, host(qj))
+        assert np.abs(host(qj1) - ref).max() <= tol * np.abs(ref).max() * (1 if prec == 0 else 5)
+    # invariants: per-node Q equal to Q, total density M
+    qn = torch.empty(K + 1, dtype=torch.complex128, device=DEV)
+    ctx.pft_node_q(qn)
+    Q = host(out["Q"])[0]
+    inv_tol = 1e-11 if prec == B.PFT_C128 else 1e-5
+    assert np.abs(host(qn) - Q).max() <= inv_tol * abs(Q)
+    total = host(out["phiA"] + out["phiB"]).sum()
+    assert abs(total - np.prod(w.n)) <= inv_tol * np.prod(w.n)
+    # sampled per-site densities through the oracle's density routine
+    rng = np.random.default_rng(5)
+    sites = rng.integers(0, np.prod(w.n), size=64)
+    qs = np.empty((K + 1, 1, 1, 64), complex)
+    qds = np.empty_like(qs)
+    buf = torch.empty(w.n, dtype=torch.complex128, device=DEV)
+    for j in range(K + 1):
+        ctx.pft_get_slice(0, j, buf)
+        qs[j, 0, 0] = host(buf).ravel()[sites]
+        ctx.pft_get_slice(1, j, buf)
+        qds[j, 0, 0] = host(buf).ravel()[sites]
+    small = orc.Params(1, 1, 64, 1.0, 1.0, 1.0, w.ns, w.f, w.chiN, 1.0, 0, False)
+    pa, pb, Qs, _ = orc.densities(small, qs, qds)
+    pa = pa.ravel() * Qs / Q
+    pb = pb.ravel() * Qs / Q
+    dtol = 1e-10 if prec == B.PFT_C128 else 1e-9
+    assert np.abs(host(out["phiA"]).ravel()[sites] - pa).max() <= dtol
+    assert np.abs(host(out["phiB"]).ravel()[sites] - pb).max() <= dtol
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
