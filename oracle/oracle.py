@@ -107,6 +107,7 @@ def lib():
             "or_philox4x64_10": (None, [vp, vp, vp]),
             "or_gaussian": (None, [u64, u64, u64, i32, i64, vp]),
             "or_em_update": (None, [P, vp, vp, vp, vp, f64, f64, f64, i32, u64, u64, u64]),
+            "or_adjoint": (ctypes.c_int, [P, vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -271,3 +272,12 @@ def evaluate(p: Params, wp, wm):
     H, hi = hamiltonian(p, wp, wm, Q)
     return {"phiA": phiA, "phiB": phiB, "Q": Q, "Qnode": Qn, "H": H, "h": hi,
             "K": qs.shape[0] - 1}
+
+
+def adjoint(p: Params, wp, wm):
+    """(dH/dw_+, dH/dw_-, dH/dL[3]) by reverse mode through the split steps."""
+    wp, wm = _cfield(wp, p.shape), _cfield(wm, p.shape)
+    gp, gm = np.empty_like(wp), np.empty_like(wp)
+    dL = np.zeros(3, np.complex128)
+    lib().or_adjoint(ctypes.byref(p._c()), _ptr(wp), _ptr(wm), _ptr(gp), _ptr(gm), _ptr(dL))
+    return gp, gm, dL

@@ -559,3 +559,131 @@ int or_evaluate(const or_params *p, const cplx *wp, const cplx *wm,
     free(qs); free(qds);
     return k;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Reverse-mode derivatives of H (Eq. (3)) through the discrete split steps. */
+/*                                                                           */
+/* Q = (1/M) 1^T q_K with q_{j+1} = T_j q_j.  Every step operator is complex- */
+/* symmetric (E diagonal, D symmetric because its multiplier is even in k),  */
+/* so the adjoint vector of step j is lambda_{j+1} = qd_{K-j-1}, the stored  */
+/* conjugate propagator, and                                                 */
+/*   dQ/dw_b(x) = (1/M) sum_{j in block b} lambda_{j+1}^T (dT_j/dw(x)) q_j.   */
+/* Each factor E_a = exp(-w a) contributes -a times the product of what      */
+/* stands to its left (transposed, acting on lambda) and to its right (acting */
+/* on q) at site x.  The box derivative replaces the axis factor of D_h by   */
+/* d/dL_a exp(-(2 pi m / L_a)^2 h) = exp(...) * 2 k_a^2 h / L_a.              */
+/* ------------------------------------------------------------------------ */
+
+/* u^T (dD_h/dL_a) v = (1/M) sum_k (2 k_a^2 h / L_a) e^{-|k|^2 h} U(-k) V(k),  */
+/* with U, V the unnormalised DFTs of u and v.                               */
+static cplx dbilinear(const or_params *p, double h, int axis, const cplx *u, const cplx *v)
+{
+    const int64_t M = grid_m(p);
+    cplx *U = (cplx *)malloc(sizeof(cplx) * M), *Vv = (cplx *)malloc(sizeof(cplx) * M);
+    memcpy(U, u, sizeof(cplx) * M);
+    memcpy(Vv, v, sizeof(cplx) * M);
+    dft3(p, U, -1);
+    dft3(p, Vv, -1);
+    const int n[3] = {p->nx, p->ny, p->nz};
+    const double L[3] = {p->lx, p->ly, p->lz};
+    cplx acc = 0.0;
+    for (int64_t jx = 0; jx < n[0]; jx++)
+        for (int64_t jy = 0; jy < n[1]; jy++)
+            for (int64_t jz = 0; jz < n[2]; jz++) {
+                const int64_t j[3] = {jx, jy, jz};
+                const double ka = OR_TWO_PI * or_mode((int32_t)j[axis], n[axis]) / L[axis];
+                const double d = 2.0 * ka * ka * h / L[axis] * exp(-ksq(p, jx, jy, jz) * h);
+                const int64_t mx = (n[0] - jx) % n[0], my = (n[1] - jy) % n[1], mz = (n[2] - jz) % n[2];
+                acc += d * U[(mx * n[1] + my) * n[2] + mz] * Vv[(jx * n[1] + jy) * n[2] + jz];
+            }
+    free(U);
+    free(Vv);
+    return acc / (double)M;
+}
+
+static void copy_mul(cplx *dst, const cplx *src, const cplx *w, double a, int64_t M)
+{
+    for (int64_t x = 0; x < M; x++) dst[x] = src[x] * cexp(-w[x] * a);
+}
+
+/*
+ * dH/dw_+(x), dH/dw_-(x) (holomorphic derivatives, per site, not per unit
+ * volume) and dH/dL_a for a = x, y, z (each edge varied alone, the grid and
+ * the fields' values on it held fixed).  Returns K.
+ */
+int or_adjoint(const or_params *p, const cplx *wp, const cplx *wm, cplx *dHdwp, cplx *dHdwm, cplx *dHdL)
+{
+    const int64_t M = grid_m(p);
+    double *h = (double *)malloc(sizeof(double) * (p->ns + 2));
+    int32_t *blk = (int32_t *)malloc(sizeof(int32_t) * (p->ns + 2));
+    int32_t J;
+    const int K = or_contour(p->ns, p->f, h, blk, &J);
+    cplx *qs = (cplx *)malloc(sizeof(cplx) * (K + 1) * M);
+    cplx *qds = (cplx *)malloc(sizeof(cplx) * (K + 1) * M);
+    cplx *wA = (cplx *)malloc(sizeof(cplx) * M), *wB = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *G[2] = {(cplx *)calloc(M, sizeof(cplx)), (cplx *)calloc(M, sizeof(cplx))};
+    cplx *t[12];
+    for (int i = 0; i < 12; i++) t[i] = (cplx *)malloc(sizeof(cplx) * M);
+    or_block_fields(p, wp, wm, wA, wB);
+    or_propagate(p, wp, wm, qs, qds);
+    cplx Q = 0.0;
+    for (int64_t x = 0; x < M; x++) Q += qs[(int64_t)K * M + x];
+    Q /= (double)M;
+    cplx dQdL[3] = {0.0, 0.0, 0.0};
+
+    for (int j = 0; j < K; j++) {
+        const double hj = h[j];
+        const cplx *w = blk[j] == 0 ? wA : wB;
+        const cplx *q = qs + (int64_t)j * M;
+        const cplx *lam = qds + (int64_t)(K - j - 1) * M;   /* lambda_{j+1} */
+        cplx *g = G[blk[j]];
+        /* full path: F = E_{h/2} D_h E_{h/2} applied to q and to lambda */
+        cplx *e2q = t[0], *e2l = t[1], *Fq = t[2], *Fl = t[3];
+        copy_mul(e2q, q, w, hj / 2, M);
+        copy_mul(e2l, lam, w, hj / 2, M);
+        memcpy(Fq, e2q, sizeof(cplx) * M); or_diffuse(p, hj, Fq); copy_mul(Fq, Fq, w, hj / 2, M);
+        memcpy(Fl, e2l, sizeof(cplx) * M); or_diffuse(p, hj, Fl); copy_mul(Fl, Fl, w, hj / 2, M);
+        if (p->scheme == OR_SPLIT2) {
+            for (int64_t x = 0; x < M; x++)
+                g[x] += -(hj / 2) * lam[x] * Fq[x] - (hj / 2) * Fl[x] * q[x];
+            for (int a = 0; a < 3; a++) dQdL[a] += dbilinear(p, hj, a, e2l, e2q);
+            continue;
+        }
+        /* half path: A = D_{h/2} E_{h/4} (.), H = E_{h/4} D_{h/2} E_{h/2} A */
+        cplx *e4q = t[4], *e4l = t[5], *Aq = t[6], *Al = t[7], *Hq = t[8], *Hl = t[9];
+        copy_mul(e4q, q, w, hj / 4, M);
+        copy_mul(e4l, lam, w, hj / 4, M);
+        memcpy(Aq, e4q, sizeof(cplx) * M); or_diffuse(p, hj / 2, Aq);
+        memcpy(Al, e4l, sizeof(cplx) * M); or_diffuse(p, hj / 2, Al);
+        cplx *e2Aq = t[10], *e2Al = t[11];
+        copy_mul(e2Aq, Aq, w, hj / 2, M);
+        copy_mul(e2Al, Al, w, hj / 2, M);
+        memcpy(Hq, e2Aq, sizeof(cplx) * M); or_diffuse(p, hj / 2, Hq); copy_mul(Hq, Hq, w, hj / 4, M);
+        memcpy(Hl, e2Al, sizeof(cplx) * M); or_diffuse(p, hj / 2, Hl); copy_mul(Hl, Hl, w, hj / 4, M);
+        for (int64_t x = 0; x < M; x++) {
+            const cplx E2 = cexp(-w[x] * (hj / 2));
+            const cplx half = -(hj / 4) * lam[x] * Hq[x] - (hj / 2) * Al[x] * E2 * Aq[x] - (hj / 4) * Hl[x] * q[x];
+            const cplx full = -(hj / 2) * lam[x] * Fq[x] - (hj / 2) * Fl[x] * q[x];
+            g[x] += (4.0 / 3.0) * half - (1.0 / 3.0) * full;
+        }
+        for (int a = 0; a < 3; a++)
+            dQdL[a] += (4.0 / 3.0) * (dbilinear(p, hj / 2, a, e4l, e2Aq) + dbilinear(p, hj / 2, a, e2Al, e4q))
+                       - (1.0 / 3.0) * dbilinear(p, hj, a, e2l, e2q);
+    }
+    const double V = p->lx * p->ly * p->lz, dV = V / (double)M;
+    cplx S = 0.0;
+    for (int64_t x = 0; x < M; x++) {
+        /* dQ/dw_+ = i (dQ/dw_A + dQ/dw_B), dQ/dw_- = dQ/dw_B - dQ/dw_A, dQ/dw_b = G_b / M */
+        const cplx dQp = I * (G[0][x] + G[1][x]) / (double)M;
+        const cplx dQm = (G[1][x] - G[0][x]) / (double)M;
+        dHdwp[x] = -I * p->C * dV - p->C * V * dQp / Q;
+        dHdwm[x] = 2.0 * p->C * dV * wm[x] / p->chiN - p->C * V * dQm / Q;
+        S += wm[x] * wm[x] / p->chiN - I * wp[x];
+    }
+    const double L[3] = {p->lx, p->ly, p->lz};
+    for (int a = 0; a < 3; a++)
+        dHdL[a] = p->C * S * dV / L[a] - p->C * (V / L[a]) * clog(Q) - p->C * V * (dQdL[a] / (double)M) / Q;
+    for (int i = 0; i < 12; i++) free(t[i]);
+    free(G[0]); free(G[1]); free(wA); free(wB); free(qs); free(qds); free(h); free(blk);
+    return K;
+}
