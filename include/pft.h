@@ -139,6 +139,24 @@ pft_status pft_hamiltonian(pft_ctx* ctx, const double* w_plus, const double* w_m
 pft_status pft_cl_step(pft_ctx* ctx, double* w_plus, double* w_minus, const pft_step* step,
                        double* phi_a, double* phi_b, double* Q, double* H);
 
+/* Reverse-mode derivatives of H (Eq. (3)) through the K discrete split steps
+ * of the context's scheme, with q checkpointed every ckpt_every nodes
+ * (0: ceil(sqrt(K))) and each segment recomputed once: memory ~(5 sqrt(K) + 15)
+ * extra fields instead of K.  The adjoint vector of step j is the conjugate
+ * propagator (every split step is complex-symmetric), so this is one
+ * checkpointed forward sweep, one segment recompute and one q-dagger sweep
+ * with per-step accumulation in FP64 (Neumaier).
+ * Outputs (device): dH_dwplus, dH_dwminus -- [nx][ny][nz] complex128, the
+ * holomorphic derivative dH/dw at each grid point (not per unit volume);
+ * dH_dL -- 3 complex128 (may be NULL): dH/dL_x, dH/dL_y, dH/dL_z with each box
+ * edge varied alone and the field values on the grid held fixed (the diagonal
+ * box stress times the volume over the edge); H -- complex128 (may be NULL),
+ * the Hamiltonian of these fields.  Overwrites the context's field tables and
+ * Q, so pft_densities / pft_hamiltonian need a new pft_propagate afterwards.
+ * Errors: PFT_E_INVALID, PFT_E_NOMEM, PFT_E_DEVICE. */
+pft_status pft_adjoint(pft_ctx* ctx, const double* w_plus, const double* w_minus, int32_t ckpt_every,
+                       double* dH_dwplus, double* dH_dwminus, double* dH_dL, double* H);
+
 /* Per-node diagnostic Qnode[j] = (1/M) sum_x q_j(x) qd_{K-j}(x), j = 0..K,
  * from the last propagate; equal to Q in exact arithmetic for every node
  * because each split step is complex-symmetric.  qnode: 2*(K+1) doubles of
@@ -200,6 +218,12 @@ typedef enum {
  * each array counted once).  Any output pointer may be NULL.
  * Errors: PFT_E_INVALID, PFT_E_STATE (end without begin), PFT_E_DEVICE. */
 pft_status pft_profile_begin(pft_ctx* ctx);
+/* Measurement hook (no context): a plain streaming copy of `bytes` bytes
+ * (a multiple of 16) from src to dst, both device memory, 16-byte aligned, not
+ * overlapping, enqueued on hip_stream.  Its hardware-counter readings give the
+ * scale that converts other kernels' counter readings into bytes.
+ * Errors: PFT_E_INVALID, PFT_E_DEVICE. */
+pft_status pft_copy_probe(const void* src, void* dst, int64_t bytes, void* hip_stream);
 pft_status pft_profile_end(pft_ctx* ctx, double* ms, int64_t* launches, double* bytes);
 
 #ifdef __cplusplus

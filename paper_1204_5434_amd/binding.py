@@ -29,7 +29,7 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_num_steps", "pft_propagate", "pft_densities", "pft_hamiltonian", "pft_cl_step",
            "pft_node_q", "pft_get_slice", "pft_apply_step", "pft_diffuse", "pft_debug_kgrid",
            "pft_status_flags", "pft_noise_words", "pft_noise_normals", "pft_profile_begin",
-           "pft_profile_end")
+           "pft_profile_end", "pft_copy_probe", "pft_adjoint")
 
 KERNEL_KINDS = ("tables", "zpass", "ypass", "xpass", "density", "reduce")
 
@@ -87,6 +87,8 @@ def load() -> ctypes.CDLL:
             "pft_noise_normals": (i32, [u64, u64, u64, i32, i64, vp, vp]),
             "pft_profile_begin": (i32, [vp]),
             "pft_profile_end": (i32, [vp, vp, vp, vp]),
+            "pft_copy_probe": (i32, [vp, vp, i64, vp]),
+            "pft_adjoint": (i32, [vp, vp, vp, i32, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -227,6 +229,13 @@ class Context:
             self._check(st)
         return flags.value
 
+    def pft_adjoint(self, w_plus, w_minus, dH_dwplus, dH_dwminus, dH_dL=None, H=None, ckpt_every: int = 0):
+        self._check(load().pft_adjoint(self._h, _field(w_plus, self.shape, "w_plus"),
+                                       _field(w_minus, self.shape, "w_minus"), int(ckpt_every),
+                                       _field(dH_dwplus, self.shape, "dH_dwplus"),
+                                       _field(dH_dwminus, self.shape, "dH_dwminus"),
+                                       _opt(dH_dL, (3,), "dH_dL"), _opt(H, (1,), "H")))
+
     def pft_profile_begin(self):
         self._check(load().pft_profile_begin(self._h))
 
@@ -267,3 +276,15 @@ def pft_noise_normals(seed: int, replica: int, step: int, field: int, M: int, de
     if st != PFT_OK:
         raise PftError(st, "pft_noise_normals failed")
     return out
+
+
+def pft_copy_probe(src: torch.Tensor, dst: torch.Tensor):
+    """Plain device copy of src into dst through the library's copy kernel."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst must be contiguous CUDA tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    st = load().pft_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, _stream())
+    if st != PFT_OK:
+        raise PftError(st, "pft_copy_probe failed")

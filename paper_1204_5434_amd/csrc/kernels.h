@@ -41,6 +41,9 @@ struct ZArgs {
     const cx<T>* En;  // E4 table of the step being started (NULL: E = 1)
     const T* gh_n;    // its z factors for h/2 and h
     const T* gf_n;
+    cx<T>* hcap;      // if set: the completed step's last diffused value before its
+                      // final field multiply (Dz U for the Richardson step, V for the
+                      // plain split), for the reverse-mode sweep
 };
 
 template <int N1, int N2>
@@ -82,26 +85,34 @@ __global__ __launch_bounds__((ZShape<N1, N2>::kThreads)) void k_zpass(ZArgs<T> A
     };
 
     cx<T> q[N1];
+    cx<T> e[N1];        // field table of the completed step, reused for the next when shared
+    bool have_e = false;
     if (A.has_prev) {
         if (A.scheme == kSchemeRQM4) {
             load(A.U, q);
             diffuse<N1, N2>(q, t, sh, lay, A.gh_p);
+            if (A.hcap) store(A.hcap, q);
             constexpr T third = T(1.0 / 3.0);
+            if (A.Ep) {
+                load(A.Ep, e);
+                have_e = true;
+            }
             if (act) {
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    const int64_t o = base + i * N2;
-                    const cx<T> u = A.Ep ? q[i] * A.Ep[o] : q[i];
-                    q[i] = third * (T(4) * u - A.V[o]);
+                    const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
+                    q[i] = third * (T(4) * u - A.V[base + i * N2]);
                 });
             }
         } else {
             load(A.V, q);
-            if (A.Ep && act) {
+            if (A.hcap) store(A.hcap, q);
+            if (A.Ep) {
+                load(A.Ep, e);
+                have_e = true;
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    const cx<T> e = A.Ep[base + i * N2];
-                    q[i] = q[i] * (e * e);
+                    q[i] = q[i] * (e[i] * e[i]);
                 });
             }
         }
@@ -115,12 +126,12 @@ __global__ __launch_bounds__((ZShape<N1, N2>::kThreads)) void k_zpass(ZArgs<T> A
     if (A.has_next) {
         // q <- E4 q (half path start) and w <- E4 E4 q (full path start)
         cx<T> w[N1];
-        if (A.En && act) {
+        if (A.En) {
+            if (!(have_e && A.En == A.Ep)) load(A.En, e);
             sfor<0, N1>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                const cx<T> e = A.En[base + i * N2];
-                q[i] = q[i] * e;
-                w[i] = q[i] * e;
+                q[i] = q[i] * e[i];
+                w[i] = q[i] * e[i];
             });
         } else {
             sfor<0, N1>([&](auto I) { w[decltype(I)::value] = q[decltype(I)::value]; });
@@ -140,6 +151,8 @@ struct SOps {
     const T* g1;     // first diffusion factor; NULL leaves the array untouched
     const cx<T>* e;  // E4 table: multiply by E4^2 after the first diffusion (NULL: none)
     const T* g2;     // second diffusion factor after the multiply (NULL: none)
+    cx<T>* acap;     // if set: store the array after the first diffusion (before the
+                     // multiply), for the reverse-mode sweep
 };
 
 template <typename T>
@@ -183,17 +196,27 @@ __global__ __launch_bounds__((SShape<T, N2>::kThreads)) void k_spass(SArgs<T> A)
     const int64_t step = (int64_t)N2 * A.S;
     const LayS<N2, TC> lay{c};
 
-    auto run = [&](cx<T>* X, const SOps<T>& op) {
-        if (!op.g1) return;
-        cx<T> a[N1];
+    auto ldX = [&](const cx<T>* X, cx<T>(&a)[N1]) {
         if (act) {
             sfor<0, N1>([&](auto I) { a[decltype(I)::value] = X[base + decltype(I)::value * step]; });
         } else {
             sfor<0, N1>([&](auto I) { a[decltype(I)::value] = cx<T>{T(0), T(0)}; });
         }
+    };
+    auto stX = [&](cx<T>* X, const cx<T>(&a)[N1]) {
+        if (act) sfor<0, N1>([&](auto I) { X[base + decltype(I)::value * step] = a[decltype(I)::value]; });
+    };
+    // one array: diffuse, [capture], [multiply by e2 = E4^2, diffuse again]
+    auto run = [&](cx<T>* X, const SOps<T>& op, const cx<T>(&e2)[N1], bool have_e2) {
+        if (!op.g1) return;
+        cx<T> a[N1];
+        ldX(X, a);
         diffuse<N1, N2>(a, t, sh, lay, op.g1);
-        if (op.e) {
-            if (act) {
+        if (op.acap) stX(op.acap, a);
+        if (AXIS == 0 && op.e) {  // field multiplies happen only in the x pass
+            if (have_e2) {
+                sfor<0, N1>([&](auto I) { a[decltype(I)::value] = a[decltype(I)::value] * e2[decltype(I)::value]; });
+            } else if (act) {
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     const cx<T> e = op.e[base + i * step];
@@ -202,10 +225,19 @@ __global__ __launch_bounds__((SShape<T, N2>::kThreads)) void k_spass(SArgs<T> A)
             }
             if (op.g2) diffuse<N1, N2>(a, t, sh, lay, op.g2);
         }
-        if (act) sfor<0, N1>([&](auto I) { X[base + decltype(I)::value * step] = a[decltype(I)::value]; });
+        stX(X, a);
     };
-    run(A.U, A.opU);
-    run(A.V, A.opV);
+    cx<T> e2[N1];
+    if (AXIS == 0 && A.opU.g1 && A.opV.g1 && A.opU.e && A.opU.e == A.opV.e) {
+        // both arrays take the same field table: read it once
+        ldX(A.opU.e, e2);
+        sfor<0, N1>([&](auto I) { e2[decltype(I)::value] = e2[decltype(I)::value] * e2[decltype(I)::value]; });
+        run(A.V, A.opV, e2, true);
+        run(A.U, A.opU, e2, true);
+    } else {
+        run(A.U, A.opU, e2, false);
+        run(A.V, A.opV, e2, false);
+    }
 }
 
 // ------------------------------------------------------------ launchers ----

@@ -219,7 +219,8 @@ __global__ __launch_bounds__(kRedThreads) void k_ham_partials(const double2* __r
 // H = C dV S - C V Log Q (principal branch), h = H / (C V).
 __global__ __launch_bounds__(kRedThreads) void k_ham_final(const double2* __restrict__ partials, int np, double C,
                                                            double dV, double V, const double2* __restrict__ Qp,
-                                                           double2* __restrict__ H, double2* __restrict__ hint)
+                                                           double2* __restrict__ H, double2* __restrict__ hint,
+                                                           double2* __restrict__ Sout)
 {
     __shared__ double2 sh[kRedThreads];
     NSum re, im;
@@ -235,6 +236,7 @@ __global__ __launch_bounds__(kRedThreads) void k_ham_final(const double2* __rest
         const double2 h = make_double2(C * dV * s.x - C * V * lr, C * dV * s.y - C * V * li);
         *H = h;
         if (hint) *hint = make_double2(h.x / (C * V), h.y / (C * V));
+        if (Sout) *Sout = s;
     }
 }
 
@@ -337,6 +339,189 @@ __global__ void k_update(UpdArgs a)
     }
 }
 
+// ------------------------------------------------------------ reverse mode --
+// Per-step contribution to dQ/dw_b (times M) of step j, accumulated in FP64
+// with Neumaier compensation into the block's (sum, comp) arrays.  With
+// lam1 = lambda_{j+1}, lam0 = lambda_j, the captures A = D_{h/2} E4 (.),
+// B = D_{h/2}(E2 A) (so the half step is E4 B) and E2 = E4^2, the derivative of
+// the Richardson step of Eq. (12) sums the three field factors of the half
+// path and the two of the full path; eliminating the full path through
+// q_{j+1} = (4 E4 Bq - Fq)/3 gives
+//   g = (h/3)(lam1 E4 Bq + E4 Bl q0) - (h/2)(lam1 q1 + lam0 q0) - (2h/3) Al E2 Aq.
+// The plain split step gives g = -(h/2)(lam1 q1 + lam0 q0).
+template <typename T>
+struct AccArgs {
+    const cx<T>* lam1;
+    const cx<T>* lam0;
+    const cx<T>* Al;
+    const cx<T>* Bl;
+    const cx<T>* q0;
+    const cx<T>* q1;
+    const cx<T>* Aq;
+    const cx<T>* Bq;
+    const cx<T>* E4;
+    double h;
+    int rqm4;
+    int64_t M;
+    double2* Gs;
+    double2* Gc;
+};
+
+__device__ __forceinline__ double2 d2(double re, double im) { return make_double2(re, im); }
+template <typename T>
+__device__ __forceinline__ double2 wide(cx<T> v) { return make_double2(double(v.re), double(v.im)); }
+
+__device__ __forceinline__ void nacc(double& s, double& c, double x)
+{
+    const double t = s + x;
+    if (fabs(s) >= fabs(x))
+        c += (s - t) + x;
+    else
+        c += (x - t) + s;
+    s = t;
+}
+
+template <typename T>
+__global__ void k_adj_accum(AccArgs<T> a)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.M; x += (int64_t)gridDim.x * blockDim.x) {
+        const double2 l1 = wide(a.lam1[x]), l0 = wide(a.lam0[x]), q0 = wide(a.q0[x]), q1 = wide(a.q1[x]);
+        const double2 tr = cmul(l1, q1), tl = cmul(l0, q0);
+        double2 g = d2(-0.5 * a.h * (tr.x + tl.x), -0.5 * a.h * (tr.y + tl.y));
+        if (a.rqm4) {
+            const double2 e4 = wide(a.E4[x]);
+            const double2 e2 = cmul(e4, e4);
+            const double2 u = cmul(l1, cmul(e4, wide(a.Bq[x])));
+            const double2 v = cmul(cmul(e4, wide(a.Bl[x])), q0);
+            const double2 m = cmul(cmul(wide(a.Al[x]), e2), wide(a.Aq[x]));
+            g.x += a.h / 3.0 * (u.x + v.x) - 2.0 * a.h / 3.0 * m.x;
+            g.y += a.h / 3.0 * (u.y + v.y) - 2.0 * a.h / 3.0 * m.y;
+        }
+        double2 s = a.Gs[x], c = a.Gc[x];
+        nacc(s.x, c.x, g.x);
+        nacc(s.y, c.y, g.y);
+        a.Gs[x] = s;
+        a.Gc[x] = c;
+    }
+}
+
+// dH/dw_+ = -i C dV [1 + (G_A + G_B)/Q],  dH/dw_- = C dV [2 w_-/chiN - (G_B - G_A)/Q],
+// from dQ/dw_+ = i (G_A + G_B)/M, dQ/dw_- = (G_B - G_A)/M and dV = V/M.
+__global__ void k_adj_final(const double2* __restrict__ G, int64_t M, const double2* __restrict__ wm,
+                            const double2* __restrict__ Qp, double C, double dV, double chiN,
+                            double2* __restrict__ dwp, double2* __restrict__ dwm)
+{
+    const double2 Q = *Qp;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
+        // G layout: [A sum][A comp][B sum][B comp]
+        const double2 ga = d2(G[x].x + G[M + x].x, G[x].y + G[M + x].y);
+        const double2 gb = d2(G[2 * M + x].x + G[3 * M + x].x, G[2 * M + x].y + G[3 * M + x].y);
+        const double2 sp = cdiv(d2(ga.x + gb.x, ga.y + gb.y), Q);
+        const double2 sm = cdiv(d2(gb.x - ga.x, gb.y - ga.y), Q);
+        // -i C dV (1 + sp)
+        dwp[x] = d2(C * dV * sp.y, -C * dV * (1.0 + sp.x));
+        const double2 w = wm[x];
+        dwm[x] = d2(C * dV * (2.0 * w.x / chiN - sm.x), C * dV * (2.0 * w.y / chiN - sm.y));
+    }
+}
+
+// Box-derivative terms of one step.  The L_a derivative of a diffusion D_h'
+// multiplies its factor by 2 k_a^2 h'/L_a, i.e. u^T dD/dL_a v = (2h'/L_a) u^T
+// (-d^2/dx_a^2) D_h' v.  S[X*3 + a] hold -d^2/dx_a^2 of the captures
+// X = B (= D_{h/2} E2 Aq), A (= D_{h/2} E4 q), C (= D_h E2 q); the matching
+// left vectors are E4 lam1, E2 Al and E2 lam1.  Per block, the three axis sums
+// are added to acc[a][block].
+template <typename T>
+struct StressArgs {
+    const cx<T>* S[9];
+    const cx<T>* lam1;
+    const cx<T>* Al;
+    const cx<T>* E4;
+    double coefB[3], coefA[3], coefC[3];
+    int rqm4;
+    int64_t M;
+    double2* acc;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_stress_dot(StressArgs<T> a)
+{
+    __shared__ double2 sh[kRedThreads];
+    NSum sr[3], si[3];
+    for (int64_t x = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; x < a.M; x += (int64_t)gridDim.x * kRedThreads) {
+        const double2 e4 = wide(a.E4[x]);
+        const double2 e2 = cmul(e4, e4);
+        const double2 l1 = wide(a.lam1[x]);
+        const double2 uC = cmul(e2, l1);
+        double2 uB = d2(0, 0), uA = d2(0, 0);
+        if (a.rqm4) {
+            uB = cmul(e4, l1);
+            uA = cmul(e2, wide(a.Al[x]));
+        }
+        for (int ax = 0; ax < 3; ++ax) {
+            double2 v = cmul(uC, wide(a.S[6 + ax][x]));
+            v = d2(a.coefC[ax] * v.x, a.coefC[ax] * v.y);
+            if (a.rqm4) {
+                const double2 b = cmul(uB, wide(a.S[ax][x]));
+                const double2 c = cmul(uA, wide(a.S[3 + ax][x]));
+                v.x += a.coefB[ax] * b.x + a.coefA[ax] * c.x;
+                v.y += a.coefB[ax] * b.y + a.coefA[ax] * c.y;
+            }
+            sr[ax].add(v.x);
+            si[ax].add(v.y);
+        }
+    }
+    for (int ax = 0; ax < 3; ++ax) {
+        const double2 s = block_sum(make_double2(sr[ax].value(), si[ax].value()), sh);
+        if (threadIdx.x == 0) {
+            double2 t = a.acc[ax * gridDim.x + blockIdx.x];
+            a.acc[ax * gridDim.x + blockIdx.x] = d2(t.x + s.x, t.y + s.y);
+        }
+        __syncthreads();
+    }
+}
+
+// dH/dL_a = C dV S / L_a - C (V/L_a) Log Q - C V (dQ/dL_a)/Q with
+// dQ/dL_a = sums[a] / M and S = sum_x [w_-^2/chiN - i w_+].
+__global__ void k_stress_final(const double2* __restrict__ sums, const double2* __restrict__ Sp,
+                               const double2* __restrict__ Qp, double C, double lx, double ly, double lz,
+                               int64_t M, double2* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double2 Q = *Qp, S = *Sp;
+    const double V = lx * ly * lz, dV = V / (double)M;
+    const double L[3] = {lx, ly, lz};
+    const double2 lq = d2(0.5 * log(Q.x * Q.x + Q.y * Q.y), atan2(Q.y, Q.x));
+    for (int a = 0; a < 3; ++a) {
+        const double2 r = cdiv(d2(sums[a].x / (double)M, sums[a].y / (double)M), Q);
+        out[a] = d2(C * dV * S.x / L[a] - C * V / L[a] * lq.x - C * V * r.x,
+                    C * dV * S.y / L[a] - C * V / L[a] * lq.y - C * V * r.y);
+    }
+}
+
+__global__ void k_fill_zero(double2* __restrict__ p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_double2(0.0, 0.0);
+}
+
+template <typename T>
+__global__ void k_copy(const cx<T>* __restrict__ src, cx<T>* __restrict__ d0, cx<T>* __restrict__ d1, int64_t M)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
+        const cx<T> v = src[x];
+        d0[x] = v;
+        d1[x] = v;
+    }
+}
+
+// Plain streaming copy (16 bytes per lane per iteration).
+__global__ void k_copy_probe(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // ============================================================== host side ==
 
 int grid_for(int64_t n, int threads, int cap = 8192)
@@ -411,6 +596,12 @@ struct pft_ctx {
     int nparts = 0;
     bool propagated = false;
     std::string err;
+    // reverse mode: working-precision slices and FP64 accumulators, allocated
+    // on the first pft_adjoint call for its checkpoint interval
+    int adj_kc = 0;
+    void* adj = nullptr;
+    double2* adjG = nullptr;    // [A sum][A comp][B sum][B comp], M each
+    double2* adjAcc = nullptr;  // [3][nparts] box-derivative partials
     // profiling: event pairs recorded around each launch while prof is set
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -492,14 +683,23 @@ cx<T>* slice(void* store, const pft_ctx* c, int node)
     return static_cast<cx<T>*>(store) + (size_t)node * c->M;
 }
 
+// The pair of work arrays a pipeline of passes runs on (half-step path U,
+// full-step path V); NULL members mean the context's own pair.
+struct Work {
+    void* U = nullptr;
+    void* V = nullptr;
+};
+
 // Z pass completing step `prev` (-1: none) and starting step `next` (-1: none).
 template <typename T>
-pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout)
+pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout, const Work& w = Work(),
+                 cx<T>* hcap = nullptr)
 {
     pft::ZArgs<T> a{};
     a.nlines = (int64_t)c->p.nx * c->p.ny;
-    a.U = static_cast<cx<T>*>(c->U);
-    a.V = static_cast<cx<T>*>(c->V);
+    a.U = static_cast<cx<T>*>(w.U ? w.U : c->U);
+    a.V = static_cast<cx<T>*>(w.V ? w.V : c->V);
+    a.hcap = hcap;
     a.qin = qin;
     a.qout = qout;
     a.scheme = c->p.scheme;
@@ -522,6 +722,7 @@ pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout)
     else if (qin) bytes += E;
     if (qout) bytes += E;
     if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
+    if (hcap) bytes += E;
     ProfScope ps(c, PFT_K_ZPASS, bytes);
     PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, a, c->stream));
     return PFT_OK;
@@ -529,15 +730,17 @@ pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout)
 
 // Strided pass along axis 0 (x) or 1 (y).
 template <typename T>
-pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV)
+pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV, const Work& w = Work())
 {
     pft::SArgs<T> a{};
-    a.U = static_cast<cx<T>*>(c->U);
-    a.V = static_cast<cx<T>*>(c->V);
+    a.U = static_cast<cx<T>*>(w.U ? w.U : c->U);
+    a.V = static_cast<cx<T>*>(w.V ? w.V : c->V);
     a.opU = opU;
     a.opV = opV;
     const double E = (double)c->elem * (double)c->M;
     double bytes = (opU.g1 ? 2 * E : 0) + (opV.g1 ? 2 * E : 0);
+    if (opU.g1 && opU.acap) bytes += E;
+    if (opV.g1 && opV.acap) bytes += E;
     if (opU.g1 && opU.e) bytes += E;
     if (opV.g1 && opV.e && !(opU.g1 && opU.e == opV.e)) bytes += E;
     ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes);
@@ -554,24 +757,27 @@ pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV)
     return PFT_OK;
 }
 
-// The Y1, X, Y2 passes of step j (Y, X for the plain split).
+// The Y1, X, Y2 passes of step j (Y, X for the plain split).  capA / capC,
+// if set, receive D_{h/2} E4 q (half path after its first diffusion) and
+// D_h E2 q (full path before its last multiply) from the x pass.
 template <typename T>
-pft_status step_body(pft_ctx* c, int j)
+pft_status step_body(pft_ctx* c, int j, const Work& w = Work(), cx<T>* capA = nullptr, cx<T>* capC = nullptr)
 {
     const int hd = c->hid[j];
     const cx<T>* e = etab<T>(c, c->kind[j]);
     const pft::SOps<T> none{nullptr, nullptr, nullptr};
     pft_status s;
     if (c->p.scheme == PFT_RQM4) {
-        s = spass<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, {gptr<T>(c, hd, 1, 1), nullptr, nullptr});
+        s = spass<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, {gptr<T>(c, hd, 1, 1), nullptr, nullptr}, w);
         if (s) return s;
-        s = spass<T>(c, 0, {gptr<T>(c, hd, 0, 0), e, gptr<T>(c, hd, 0, 0)}, {gptr<T>(c, hd, 1, 0), e, nullptr});
+        s = spass<T>(c, 0, {gptr<T>(c, hd, 0, 0), e, gptr<T>(c, hd, 0, 0), capA},
+                     {gptr<T>(c, hd, 1, 0), e, nullptr, capC}, w);
         if (s) return s;
-        return spass<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, none);
+        return spass<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, none, w);
     }
-    s = spass<T>(c, 1, none, {gptr<T>(c, hd, 1, 1), nullptr, nullptr});
+    s = spass<T>(c, 1, none, {gptr<T>(c, hd, 1, 1), nullptr, nullptr}, w);
     if (s) return s;
-    return spass<T>(c, 0, none, {gptr<T>(c, hd, 1, 0), nullptr, nullptr});
+    return spass<T>(c, 0, none, {gptr<T>(c, hd, 1, 0), nullptr, nullptr}, w);
 }
 
 // One sweep over the K steps, forward (q) or mirrored (q-dagger), storing
@@ -593,7 +799,7 @@ pft_status sweep(pft_ctx* c, bool backward, void* store)
 }
 
 template <typename T>
-pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
+pft_status field_tables_t(pft_ctx* c, const double* wp, const double* wm)
 {
     TabDesc d{};
     d.n = 4;
@@ -609,7 +815,15 @@ pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
                        static_cast<cx<T>*>(c->E));
     }
     PFT_HIP(c, hipGetLastError());
-    pft_status s = sweep<T>(c, false, c->qs);
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
+{
+    pft_status s = field_tables_t<T>(c, wp, wm);
+    if (s) return s;
+    s = sweep<T>(c, false, c->qs);
     if (s) return s;
     s = sweep<T>(c, true, c->qds);
     if (s) return s;
@@ -621,6 +835,22 @@ pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
                        1.0 / (double)c->M, c->scal, (double2*)nullptr, c->flags);
     PFT_HIP(c, hipGetLastError());
     c->propagated = true;
+    return PFT_OK;
+}
+
+// H and h of Eq. (3) into device pointers (hint may be NULL); the local sum
+// S = sum_x [w_-^2/chiN - i w_+] is kept in scal[4].
+pft_status hamiltonian_launch(pft_ctx* c, const double* wp, const double* wm, double* H, double* hint)
+{
+    const double V = c->p.lx * c->p.ly * c->p.lz;
+    ProfScope ps(c, PFT_K_REDUCE, 2.0 * sizeof(double2) * (double)c->M);
+    hipLaunchKernelGGL(k_ham_partials, dim3(c->nparts), dim3(kRedThreads), 0, c->stream,
+                       reinterpret_cast<const double2*>(wp), reinterpret_cast<const double2*>(wm), c->M,
+                       1.0 / c->p.chiN, c->partials);
+    hipLaunchKernelGGL(k_ham_final, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, c->nparts, c->p.C,
+                       V / (double)c->M, V, c->scal, reinterpret_cast<double2*>(H), reinterpret_cast<double2*>(hint),
+                       c->scal + 4);
+    PFT_HIP(c, hipGetLastError());
     return PFT_OK;
 }
 
@@ -705,6 +935,25 @@ pft_status upload_factors(pft_ctx* c, int hid, double h)
     return PFT_OK;
 }
 
+// Spectral -d^2/dx_a^2 per axis, (2 pi m / L_a)^2 / N_a, in table slot 4.
+template <typename T>
+pft_status upload_second_derivative(pft_ctx* c)
+{
+    const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+    const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
+    for (int ax = 0; ax < 3; ++ax) {
+        std::vector<T> g(n[ax]);
+        for (int j = 0; j < n[ax]; ++j) {
+            const int m = (j <= n[ax] / 2) ? j : j - n[ax];
+            const double k = kTwoPi * m / L[ax];
+            g[j] = T(k * k / n[ax]);
+        }
+        PFT_HIP(c, hipMemcpy(const_cast<T*>(gptr<T>(c, 4, 0, ax)), g.data(), g.size() * sizeof(T),
+                             hipMemcpyHostToDevice));
+    }
+    return PFT_OK;
+}
+
 // D_h through the axis passes: u is staged in the working precision, run
 // through the z, y and x passes with the full-step factors for h (kept in a
 // spare table slot so the step tables stay intact) and read back from V.
@@ -740,11 +989,183 @@ pft_status diffuse_t(pft_ctx* c, double* u, double h)
     return PFT_OK;
 }
 
+// ---------------------------------------------------------------- adjoint --
+// Reverse mode through the K split steps.  The forward sweep keeps q only at
+// the checkpoint nodes 0, Kc, 2Kc, ... and q_K.  The adjoint vector of step j
+// is lambda_{j+1} = qd_{K-j-1} (each step operator is complex-symmetric), so
+// the lambda sweep is the q-dagger sweep run on its own work pair.  Segments
+// [a, b) are visited from the end; before the first of its steps is needed,
+// each segment is recomputed forward from its checkpoint on the context's
+// work pair, storing q_{a+1..b} and the captures A, B, C of every step.
+template <typename T>
+pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, double* dwp, double* dwm, double* dL,
+                     double* H)
+{
+    const int K = c->K;
+    const int64_t M = c->M;
+    const bool rqm4 = c->p.scheme == PFT_RQM4;
+    const int nck = (K + Kc - 1) / Kc;  // checkpoint nodes a = 0, Kc, ... < K
+    const size_t nslices = (size_t)nck + 1 + 4 * (size_t)Kc + 4 + 2 + 9;
+    if (!c->adj || c->adj_kc != Kc) {
+        if (c->adj) (void)hipFree(c->adj);
+        c->adj = nullptr;
+        if (hipMalloc(&c->adj, nslices * M * c->elem) != hipSuccess) {
+            (void)hipGetLastError();
+            return c->fail(PFT_E_NOMEM, "pft_adjoint: cannot allocate %zu slices", nslices);
+        }
+        c->adj_kc = Kc;
+    }
+    if (!c->adjG && hipMalloc((void**)&c->adjG, 4 * M * sizeof(double2)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->adjG = nullptr;
+        return c->fail(PFT_E_NOMEM, "pft_adjoint: cannot allocate accumulators");
+    }
+    if (!c->adjAcc && hipMalloc((void**)&c->adjAcc, 3 * (size_t)c->nparts * sizeof(double2)) != hipSuccess) {
+        (void)hipGetLastError();
+        c->adjAcc = nullptr;
+        return c->fail(PFT_E_NOMEM, "pft_adjoint: cannot allocate stress partials");
+    }
+    cx<T>* base = static_cast<cx<T>*>(c->adj);
+    auto sl = [&](size_t i) { return base + i * (size_t)M; };
+    auto ckpt = [&](int node) { return sl((size_t)(node / Kc)); };
+    cx<T>* qK = sl(nck);
+    size_t o = nck + 1;
+    cx<T>* segQ = sl(o); o += Kc;  // segQ[i] = q_{a+1+i}
+    cx<T>* segA = sl(o); o += Kc;
+    cx<T>* segB = sl(o); o += Kc;
+    cx<T>* segC = sl(o); o += Kc;
+    cx<T>* lam[2] = {sl(o), sl(o + 1)}; o += 2;
+    cx<T>* Al = sl(o++);
+    cx<T>* Bl = sl(o++);
+    const Work wl{sl(o), sl(o + 1)}; o += 2;
+    cx<T>* S[9];
+    for (int i = 0; i < 9; ++i) S[i] = sl(o++);
+    auto seg = [&](cx<T>* buf, int i) { return buf + (size_t)i * M; };
+
+    pft_status s = field_tables_t<T>(c, wp, wm);
+    if (s) return s;
+    // forward sweep keeping checkpoints
+    s = zpass<T>(c, -1, 0, nullptr, ckpt(0));
+    if (s) return s;
+    for (int i = 0; i < K; ++i) {
+        s = step_body<T>(c, i);
+        if (s) return s;
+        const int node = i + 1;
+        cx<T>* out = node == K ? qK : (node % Kc == 0 ? ckpt(node) : nullptr);
+        s = zpass<T>(c, i, i + 1 < K ? i + 1 : -1, nullptr, out);
+        if (s) return s;
+    }
+    hipLaunchKernelGGL((k_sum_partials<T>), dim3(c->nparts), dim3(kRedThreads), 0, c->stream, qK, M, c->partials);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, c->nparts,
+                       1.0 / (double)M, c->scal, (double2*)nullptr, c->flags);
+    PFT_HIP(c, hipGetLastError());
+    s = hamiltonian_launch(c, wp, wm, H ? H : reinterpret_cast<double*>(c->scal + 1), nullptr);
+    if (s) return s;
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(4 * M, 256)), dim3(256), 0, c->stream, c->adjG, 4 * M);
+    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, c->stream, c->adjAcc, (int64_t)3 * c->nparts);
+    PFT_HIP(c, hipGetLastError());
+
+    const pft::SOps<T> none{nullptr, nullptr, nullptr};
+    auto dtab = [&](int ax) { return gptr<T>(c, 4, 0, ax); };
+    const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
+
+    // lambda_K = 1, then the steps in reverse order
+    s = zpass<T>(c, -1, K - 1, nullptr, lam[0], wl);
+    if (s) return s;
+    int cur = 0;
+    for (int j = K - 1; j >= 0; --j) {
+        const int a = (j / Kc) * Kc, b = std::min(a + Kc, K);
+        if (j == b - 1) {
+            s = zpass<T>(c, -1, a, ckpt(a), nullptr);
+            if (s) return s;
+            for (int jj = a; jj < b; ++jj) {
+                s = step_body<T>(c, jj, Work(), rqm4 ? seg(segA, jj - a) : nullptr, rqm4 ? seg(segC, jj - a) : nullptr);
+                if (s) return s;
+                s = zpass<T>(c, jj, jj + 1 < b ? jj + 1 : -1, nullptr, seg(segQ, jj - a), Work(), seg(segB, jj - a));
+                if (s) return s;
+            }
+        }
+        s = step_body<T>(c, j, wl, rqm4 ? Al : nullptr, nullptr);
+        if (s) return s;
+        s = zpass<T>(c, j, j > 0 ? j - 1 : -1, nullptr, lam[1 - cur], wl, rqm4 ? Bl : nullptr);
+        if (s) return s;
+        const cx<T>* q0 = (j == a) ? ckpt(a) : seg(segQ, j - a - 1);
+        AccArgs<T> ac{lam[cur], lam[1 - cur], Al, Bl, q0, seg(segQ, j - a), seg(segA, j - a), seg(segB, j - a),
+                      etab<T>(c, c->kind[j]), c->h[j], rqm4 ? 1 : 0, M,
+                      c->adjG + (c->blk[j] == 0 ? 0 : 2 * M), c->adjG + (c->blk[j] == 0 ? M : 3 * M)};
+        {
+            ProfScope ps(c, PFT_K_REDUCE, (9.0 * c->elem + 64.0) * (double)M);
+            hipLaunchKernelGGL((k_adj_accum<T>), dim3(grid_for(M, 256)), dim3(256), 0, c->stream, ac);
+        }
+        PFT_HIP(c, hipGetLastError());
+        if (dL) {
+            // -d^2/dx_a^2 of each capture X (B, A, C): z out of place, y and x on copies
+            const cx<T>* X[3] = {seg(segB, j - a), seg(segA, j - a), seg(segC, j - a)};
+            if (!rqm4) X[2] = seg(segB, j - a);  // plain split: the z-pass capture is D_h E2 q
+            for (int xi = rqm4 ? 0 : 2; xi < 3; ++xi) {
+                pft::ZArgs<T> z{};
+                z.nlines = (int64_t)c->p.nx * c->p.ny;
+                z.U = S[xi * 3 + 2];
+                z.V = S[xi * 3 + 2];
+                z.qin = X[xi];
+                z.scheme = PFT_SPLIT2;
+                z.has_next = 1;
+                z.gf_n = dtab(2);
+                PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, z, c->stream));
+                hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(M, 256)), dim3(256), 0, c->stream, X[xi], S[xi * 3 + 1],
+                                   S[xi * 3 + 0], M);
+                PFT_HIP(c, hipGetLastError());
+            }
+            for (int ax = 0; ax < 2; ++ax) {  // x then y, two arrays per launch
+                const pft::SOps<T> op{dtab(ax), nullptr, nullptr};
+                if (rqm4) {
+                    s = spass<T>(c, ax, op, op, Work{S[0 * 3 + ax], S[1 * 3 + ax]});
+                    if (s) return s;
+                }
+                s = spass<T>(c, ax, op, none, Work{S[2 * 3 + ax], S[2 * 3 + ax]});
+                if (s) return s;
+            }
+            StressArgs<T> sa{};
+            for (int i = 0; i < 9; ++i) sa.S[i] = S[i];
+            sa.lam1 = lam[cur];
+            sa.Al = Al;
+            sa.E4 = etab<T>(c, c->kind[j]);
+            for (int ax = 0; ax < 3; ++ax) {
+                const double r = c->h[j] / L[ax];
+                sa.coefB[ax] = rqm4 ? 4.0 / 3.0 * r : 0.0;
+                sa.coefA[ax] = rqm4 ? 4.0 / 3.0 * r : 0.0;
+                sa.coefC[ax] = rqm4 ? -2.0 / 3.0 * r : 2.0 * r;
+            }
+            sa.rqm4 = rqm4 ? 1 : 0;
+            sa.M = M;
+            sa.acc = c->adjAcc;
+            hipLaunchKernelGGL((k_stress_dot<T>), dim3(c->nparts), dim3(kRedThreads), 0, c->stream, sa);
+            PFT_HIP(c, hipGetLastError());
+        }
+        cur = 1 - cur;
+    }
+    const double dV = c->p.lx * c->p.ly * c->p.lz / (double)M;
+    hipLaunchKernelGGL(k_adj_final, dim3(grid_for(M, 256)), dim3(256), 0, c->stream, c->adjG, M,
+                       reinterpret_cast<const double2*>(wm), c->scal, c->p.C, dV, c->p.chiN,
+                       reinterpret_cast<double2*>(dwp), reinterpret_cast<double2*>(dwm));
+    PFT_HIP(c, hipGetLastError());
+    if (dL) {
+        hipLaunchKernelGGL(k_final_sum, dim3(3), dim3(kRedThreads), 0, c->stream, c->adjAcc, c->nparts, 1.0,
+                           c->scal + 5, (double2*)nullptr, (uint32_t*)nullptr);
+        hipLaunchKernelGGL(k_stress_final, dim3(1), dim3(64), 0, c->stream, c->scal + 5, c->scal + 4, c->scal,
+                           c->p.C, c->p.lx, c->p.ly, c->p.lz, M, reinterpret_cast<double2*>(dL));
+        PFT_HIP(c, hipGetLastError());
+    }
+    return PFT_OK;
+}
+
 void free_all(pft_ctx* c)
 {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
-    void* bufs[] = {c->qs, c->qds, c->U, c->V, c->E, c->work, c->gtab, c->tau, c->phi, c->partials, c->scal, c->flags};
+    void* bufs[] = {c->qs,  c->qds,      c->U,        c->V,    c->E,     c->work,  c->gtab,
+                    c->tau, c->phi,      c->partials, c->scal, c->flags, c->adj,   c->adjG,
+                    c->adjAcc};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -831,7 +1252,7 @@ pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
     const size_t store = (size_t)(c->K + 1) * c->M * c->elem;
     bool ok = alloc(&c->qs, store) && alloc(&c->qds, store) && alloc(&c->U, c->M * c->elem) &&
               alloc(&c->V, c->M * c->elem) && alloc(&c->E, 4 * c->M * c->elem) && alloc(&c->work, 2 * c->M * c->elem) &&
-              alloc(&c->gtab, (size_t)4 * 2 * 3 * c->maxN * (c->elem / 2)) &&
+              alloc(&c->gtab, (size_t)5 * 2 * 3 * c->maxN * (c->elem / 2)) &&
               alloc((void**)&c->tau, tau.size() * sizeof(double)) && alloc((void**)&c->phi, 2 * c->M * sizeof(double2)) &&
               alloc((void**)&c->partials, (size_t)std::max(c->nparts, 64 * (c->K + 1)) * sizeof(double2)) &&
               alloc((void**)&c->scal, (size_t)(8 + c->K + 1) * sizeof(double2)) && alloc((void**)&c->flags, sizeof(uint32_t));
@@ -849,6 +1270,7 @@ pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
         const double hv = c->hval[hd] > 0 ? c->hval[hd] : ds;
         s = p.precision == PFT_C128 ? upload_factors<double>(c, hd, hv) : upload_factors<float>(c, hd, hv);
     }
+    if (s == PFT_OK) s = p.precision == PFT_C128 ? upload_second_derivative<double>(c) : upload_second_derivative<float>(c);
     if (s != PFT_OK) {
         free_all(c);
         delete c;
@@ -893,15 +1315,7 @@ pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, doubl
     if (!aligned16(wp) || !aligned16(wm) || !aligned16(H) || (hint && !aligned16(hint)))
         return c->fail(PFT_E_INVALID, "w_plus/w_minus/H must be non-null and 16-byte aligned");
     if (!c->propagated) return c->fail(PFT_E_STATE, "pft_hamiltonian needs a prior pft_propagate");
-    const double V = c->p.lx * c->p.ly * c->p.lz;
-    ProfScope ps(c, PFT_K_REDUCE, 2.0 * sizeof(double2) * (double)c->M);
-    hipLaunchKernelGGL(k_ham_partials, dim3(c->nparts), dim3(kRedThreads), 0, c->stream,
-                       reinterpret_cast<const double2*>(wp), reinterpret_cast<const double2*>(wm), c->M,
-                       1.0 / c->p.chiN, c->partials);
-    hipLaunchKernelGGL(k_ham_final, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, c->nparts, c->p.C,
-                       V / (double)c->M, V, c->scal, reinterpret_cast<double2*>(H), reinterpret_cast<double2*>(hint));
-    PFT_HIP(c, hipGetLastError());
-    return PFT_OK;
+    return hamiltonian_launch(c, wp, wm, H, hint);
 }
 
 pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, double* phi_a, double* phi_b,
@@ -998,6 +1412,22 @@ pft_status pft_status_flags(pft_ctx* c, uint32_t* flags)
     return (*flags & 1u) ? PFT_E_NONFINITE : PFT_OK;
 }
 
+pft_status pft_adjoint(pft_ctx* c, const double* wp, const double* wm, int32_t ckpt_every, double* dwp, double* dwm,
+                       double* dL, double* H)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!aligned16(wp) || !aligned16(wm) || !aligned16(dwp) || !aligned16(dwm) || (dL && !aligned16(dL)) ||
+        (H && !aligned16(H)))
+        return c->fail(PFT_E_INVALID, "pft_adjoint: pointers must be non-null (dH_dL, H optional) and 16-byte aligned");
+    if (ckpt_every < 0) return c->fail(PFT_E_INVALID, "pft_adjoint: ckpt_every must be >= 0");
+    int Kc = ckpt_every;
+    if (Kc == 0) Kc = (int)std::ceil(std::sqrt((double)c->K));
+    Kc = std::max(1, std::min(Kc, c->K));
+    c->propagated = false;  // the field tables and Q now belong to these fields
+    return c->p.precision == PFT_C128 ? adjoint_t<double>(c, wp, wm, Kc, dwp, dwm, dL, H)
+                                      : adjoint_t<float>(c, wp, wm, Kc, dwp, dwm, dL, H);
+}
+
 pft_status pft_profile_begin(pft_ctx* c)
 {
     if (!c) return PFT_E_INVALID;
@@ -1029,6 +1459,15 @@ pft_status pft_profile_end(pft_ctx* c, double* ms, int64_t* launches, double* by
     }
     c->ev_used = 0;
     return PFT_OK;
+}
+
+pft_status pft_copy_probe(const void* src, void* dst, int64_t bytes, void* stream)
+{
+    if (!aligned16(src) || !aligned16(dst) || bytes <= 0 || bytes % 16 != 0) return PFT_E_INVALID;
+    const int64_t n = bytes / 16;
+    hipLaunchKernelGGL(k_copy_probe, dim3(grid_for(n, 256, 4096)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const double2*>(src), static_cast<double2*>(dst), n);
+    return hipGetLastError() == hipSuccess ? PFT_OK : PFT_E_DEVICE;
 }
 
 pft_status pft_noise_words(uint64_t seed, uint64_t rep, uint64_t step, int32_t field, int64_t M, uint64_t* out,

@@ -1,10 +1,10 @@
 """GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
 identical seeded inputs.
 
-Bars: complex128 propagators -- |dphi| <= 1e-10, Q and H relative <= 1e-11;
-complex64 propagators (FP64 sums) -- ||dphi||/||phi|| and Q relative <= 2e-5,
-H within 2e-5 (|H| + C V) (the log Q term carries Q's relative error times
-C V); the integer k-grid and the Philox words bit-exact.
+Bars: complex128 propagators -- |dphi| <= 1e-10, Q relative <= 1e-11, H within
+1e-11 (|H| + C V); complex64 propagators (FP64 sums) -- ||dphi||/||phi|| and Q
+relative <= 2e-5, H within 2e-5 (|H| + C V) (the log Q term carries Q's
+relative error times C V); the integer k-grid and the Philox words bit-exact.
 """
 import numpy as np
 import pytest
@@ -47,6 +47,13 @@ def gparams(n, L, ns, f, chiN, C, scheme, prec):
 
 def rel(a, b):
     return abs(a - b) / abs(b)
+
+
+def h_close(got, ref, C, volume, tol):
+    """H = C dV sum(...) - C V log Q: Q's relative error e enters H as C V e,
+    so H is compared on the scale |H| + C V rather than relative to H (which
+    can be near zero, e.g. close to the disordered saddle point)."""
+    return abs(got - ref) <= tol * (abs(ref) + C * volume)
 
 
 # ----------------------------------------------------------------- noise --
@@ -155,8 +162,9 @@ def test_evaluation_fp64(orc, case):
     assert np.abs(got["phiA"] - ref["phiA"]).max() <= 1e-10
     assert np.abs(got["phiB"] - ref["phiB"]).max() <= 1e-10
     assert rel(got["Q"][0], ref["Q"]) <= 1e-11
-    assert rel(got["H"][0], ref["H"]) <= 1e-11
-    assert rel(got["h"][0], ref["h"]) <= 1e-11
+    V = case[1][0] * case[1][1] * case[1][2]
+    assert h_close(got["H"][0], ref["H"], case[5], V, 1e-11)
+    assert h_close(got["h"][0] * case[5] * V, ref["H"], case[5], V, 1e-11)
     assert np.abs(got["Qnode"] - ref["Qnode"]).max() <= 1e-11 * abs(ref["Q"])
 
 
@@ -168,10 +176,8 @@ def test_evaluation_fp32(orc, case):
     for k in ("phiA", "phiB"):
         assert np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max() <= 2e-5, k
     assert rel(got["Q"][0], ref["Q"]) <= 2e-5
-    # H = C dV sum(...) - C V log Q is a difference of two extensive terms, so
-    # Q's relative error e reaches H as C V e: the bound is 2e-5 on that scale.
-    n, L, C = case[0], case[1], case[5]
-    assert abs(got["H"][0] - ref["H"]) <= 2e-5 * (abs(ref["H"]) + C * L[0] * L[1] * L[2])
+    L, C = case[1], case[5]
+    assert h_close(got["H"][0], ref["H"], C, L[0] * L[1] * L[2], 2e-5)
 
 
 @pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
@@ -218,7 +224,8 @@ def test_scft_relaxation_trajectory(orc):
         ref = orc.evaluate(p_or, wp, wm)
         ctx.pft_cl_step(gwp, gwm, st, phiA, phiB, Q, H)
         assert np.abs(host(phiA) - ref["phiA"]).max() <= 1e-10, it
-        assert rel(host(Q)[0], ref["Q"]) <= 1e-11 and rel(host(H)[0], ref["H"]) <= 1e-11, it
+        assert rel(host(Q)[0], ref["Q"]) <= 1e-11, it
+        assert h_close(host(H)[0], ref["H"], w.C, np.prod(w.L), 1e-11), it
         wp, wm = orc.em_update(p_or, wp, wm, ref["phiA"], ref["phiB"], w.dt)
         assert np.abs(host(gwp) - wp).max() <= 1e-10 and np.abs(host(gwm) - wm).max() <= 1e-10, it
 
