@@ -108,6 +108,54 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     return {"value": rate, "ms_per_step": ms, "roofline": roof, "kernels": breakdown, "Q": [Qv.real, Qv.imag]}
 
 
+def batched_gain(binding, inputs, count: int, steps: int):
+    """Uneven replicas (grids 24-48^3, Ns 40-80): complex64 propagators, all
+    replicas per launch, field steps replayed from a HIP graph -- against the
+    same replicas advanced one at a time in the plain complex128 form."""
+    import torch
+    reps = inputs.batch_replicas(count, 1208)
+    site_steps = sum(2.0 * w.M * w.ns for w in reps)  # per field step of the whole set
+    fields = [inputs.fields(w) for w in reps]
+    out = {"replicas": count, "site_steps_per_field_step": site_steps}
+    # batched, complex64, graph
+    params = [binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, binding.PFT_C64, binding.PFT_RQM4) for w in reps]
+    bat = binding.Batch(params)
+    wp = [torch.from_numpy(f[0]).to("cuda") for f in fields]
+    wm = [torch.from_numpy(f[1]).to("cuda") for f in fields]
+    st = binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 0, 1)
+    bat.pft_batch_cl_steps(wp, wm, st, 2)  # capture + warm-up
+    bat.pft_batch_sync()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 2, 1), steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    out["batched_c64_graph"] = {"ms_per_field_step": ms, "value": site_steps / (ms * 1e-3)}
+    bat.close()
+    del wp, wm
+    # one at a time, complex128, plain launches
+    wp = [torch.from_numpy(f[0]).to("cuda") for f in fields]
+    wm = [torch.from_numpy(f[1]).to("cuda") for f in fields]
+    ctxs = [binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, binding.PFT_C128,
+                                           binding.PFT_RQM4)) for w in reps]
+    for r, c in enumerate(ctxs):  # warm-up
+        c.pft_cl_step(wp[r], wm[r], binding.pft_step(0.01, 1.0, 1.0, 1208, r, 0, 1))
+    torch.cuda.synchronize()
+    t0.record()
+    for k in range(steps):
+        for r, c in enumerate(ctxs):
+            c.pft_cl_step(wp[r], wm[r], binding.pft_step(0.01, 1.0, 1.0, 1208, r, 1 + k, 1))
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    out["single_c128_plain"] = {"ms_per_field_step": ms, "value": site_steps / (ms * 1e-3)}
+    for c in ctxs:
+        c.close()
+    out["gain"] = out["batched_c64_graph"]["value"] / out["single_c128_plain"]["value"]
+    return out
+
+
 def cpu_baseline(w, wp, wm, seconds: float):
     """The FP64 oracle on a bounded sample: forward-sweep Richardson steps of
     the same 128^3 workload on all host threads, until `seconds` elapse."""
@@ -143,6 +191,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="both", choices=["both", "f64", "f32"])
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel variants instead of timing them first")
+    ap.add_argument("--tune-file", default=None,
+                    help="load the variant table from this file if it exists, else tune and save it there")
+    ap.add_argument("--batch-replicas", type=int, default=256,
+                    help="replicas in the batched-vs-plain comparison (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the library's plain copy kernel on this many MiB (counter scale)")
     args = ap.parse_args()
@@ -172,6 +227,20 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy probe: 3 x {args.copy_probe_mib} MiB")
         del a, b
+    tuned = None
+    if args.tune_file and os.path.exists(args.tune_file):
+        binding.pft_tune_load(args.tune_file)
+        tuned = {"loaded": args.tune_file}
+        log(f"[bench] kernel variants loaded from {args.tune_file}")
+    elif not args.no_autotune:
+        sizes = sorted(set(w.n) | ({24, 32, 40, 48} if args.batch_replicas > 0 else set()))
+        tuned = {}
+        for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+            choice, times = binding.pft_autotune(prec, sizes)
+            tuned[name] = {str(n): {"z": c[0], "strided": c[1]} for n, c in choice.items()}
+        log(f"[bench] autotuned kernel variants: {tuned}")
+        if args.tune_file:
+            binding.pft_tune_save(args.tune_file)
     res = {}
     precisions = ("f64", "f32") if args.precision == "both" else (args.precision,)
     for precision in precisions:
@@ -179,6 +248,11 @@ def main():
         res[precision] = run_precision(binding, w, wp, wm, precision, args.steps, args.warmup, scheme)
         log(f"[bench] {precision}: {res[precision]['ms_per_step']:.3f} ms/eval, "
             f"{res[precision]['value']:.3e} site-steps/s, roofline {res[precision]['roofline']}")
+    batched = None
+    if args.batch_replicas > 0:
+        log(f"[bench] batched replicas: {args.batch_replicas}, {args.batch_steps} field steps")
+        batched = batched_gain(binding, inputs, args.batch_replicas, args.batch_steps)
+        log(f"[bench] batched: {batched}")
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
@@ -204,6 +278,10 @@ def main():
         "cpu_baseline": cpu,
         "kernels": main_["kernels"],
     }
+    if tuned is not None:
+        line["kernel_variants"] = tuned
+    if batched is not None:
+        line["batched"] = batched
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "dtype": "f32 propagators, f64 sums", "roofline": res["f32"]["roofline"],

@@ -197,6 +197,67 @@ pft_status pft_noise_words(uint64_t seed, uint64_t replica, uint64_t step, int32
 pft_status pft_noise_normals(uint64_t seed, uint64_t replica, uint64_t step, int32_t field,
                              int64_t M, double* out, void* hip_stream);
 
+/* ---- batches of independent replicas --------------------------------------
+ * Many independent systems (SCFT candidates or complex-Langevin replicas,
+ * each its own pft_params: grid, box, ns, f, chiN, C) advanced together.
+ * Replicas with the same grid shape form a group; every axis pass of a group
+ * is one launch over all its replicas (per-replica arguments come from device
+ * tables, uneven contour step counts are masked); groups run on their own
+ * streams; one field step of the whole batch is captured in a HIP graph and
+ * replayed.  All replicas must share precision and scheme.  This fills the
+ * GPU with small grids, which on their own cannot hide memory latency
+ * (Sec. VI notes the GPU only pays off above 512-2048 plane waves). */
+typedef struct pft_batch pft_batch;
+
+/* params: n parameter sets (host memory).  Errors: PFT_E_INVALID (n < 1,
+ * mixed precision/scheme, or a bad parameter set), PFT_E_UNSUPPORTED,
+ * PFT_E_NOMEM, PFT_E_DEVICE; on failure *out = NULL and nothing is kept. */
+pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_stream, pft_batch** out);
+void pft_batch_destroy(pft_batch* batch);
+const char* pft_batch_last_error(const pft_batch* batch);
+
+/* One evaluation of every replica (tables, both sweeps, Q, densities, H).
+ * w_plus, w_minus, phi_a, phi_b: host arrays of n device pointers (each a
+ * [nx][ny][nz] complex128 field of that replica); Q, H: device arrays of n
+ * complex128.  Errors: PFT_E_INVALID, PFT_E_DEVICE. */
+pft_status pft_batch_evaluate(pft_batch* batch, const double* const* w_plus, const double* const* w_minus,
+                              double* const* phi_a, double* const* phi_b, double* Q, double* H);
+
+/* nsteps field steps of every replica (pft_cl_step semantics, in place on
+ * the fields), replica r drawing noise with key (seed, replica + r) and step
+ * numbers step, step+1, ....  The step is captured in a HIP graph on first
+ * use and replayed; a call with other field pointers, log buffer or step
+ * parameters re-captures.  QH_log (device, may be NULL): rows of n (Q, H)
+ * complex128 pairs, row i for the i-th step of this call, up to log_rows
+ * rows.  Asynchronous; pft_batch_sync waits.  Errors: PFT_E_INVALID,
+ * PFT_E_DEVICE. */
+pft_status pft_batch_cl_steps(pft_batch* batch, double* const* w_plus, double* const* w_minus,
+                              const pft_step* step, int32_t nsteps, double* QH_log, int64_t log_rows);
+pft_status pft_batch_sync(pft_batch* batch);
+
+/* ---- autotuner ---------------------------------------------------------------
+ * Every axis length has up to three kernel variants of its passes (workgroup
+ * tile width, radix split N = N1 * N2; all give the same results to rounding).
+ * pft_autotune times every variant of the z pass and of the strided passes for
+ * each listed axis length on the current device (grids of ~4 Mi sites) and
+ * makes the fastest the default for contexts and batches created afterwards.
+ * choices (may be NULL): 2 ints per size (z variant, strided variant);
+ * timings (may be NULL): 6 doubles per size (ms per launch, z then strided,
+ * variants 0..2, -1 where a variant does not exist).  Synchronous.
+ * Errors: PFT_E_INVALID, PFT_E_UNSUPPORTED, PFT_E_NOMEM, PFT_E_DEVICE. */
+pft_status pft_autotune(int32_t precision, const int32_t* sizes, int32_t nsizes, void* hip_stream,
+                        int32_t* choices, double* timings);
+/* Save / load the table (text: "arch precision N kind variant" per line;
+ * entries for another GPU architecture are ignored).  pft_create also loads
+ * the file named by $PFT_TUNE_CACHE once per process.  Errors: PFT_E_INVALID
+ * (NULL path or file not writable / readable). */
+pft_status pft_tune_save(const char* path);
+pft_status pft_tune_load(const char* path);
+/* Force kernel variant `variant` on one axis (0 = x, 1 = y, 2 = z) of a
+ * context (checking every variant against the oracle).  Errors:
+ * PFT_E_INVALID, PFT_E_UNSUPPORTED (no such variant). */
+pft_status pft_set_variant(pft_ctx* ctx, int32_t axis, int32_t variant);
+
 /* Kernel kinds reported by the profiling calls below. */
 typedef enum {
     PFT_K_TABLES = 0,  /* field operator tables exp(-w h/4)                     */

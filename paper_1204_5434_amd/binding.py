@@ -29,7 +29,13 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_num_steps", "pft_propagate", "pft_densities", "pft_hamiltonian", "pft_cl_step",
            "pft_node_q", "pft_get_slice", "pft_apply_step", "pft_diffuse", "pft_debug_kgrid",
            "pft_status_flags", "pft_noise_words", "pft_noise_normals", "pft_profile_begin",
-           "pft_profile_end", "pft_copy_probe", "pft_adjoint")
+           "pft_profile_end", "pft_copy_probe", "pft_adjoint", "pft_batch_create", "pft_batch_destroy",
+           "pft_batch_last_error", "pft_batch_evaluate", "pft_batch_cl_steps", "pft_batch_sync",
+           "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant")
+
+# Kernel variants per axis length (variant 0 always exists).
+VARIANTS = {8: (0,), 12: (0,), 16: (0, 1, 2), 20: (0,), 24: (0, 1), 32: (0, 1, 2), 40: (0, 1), 48: (0, 1),
+            64: (0, 1, 2), 80: (0,), 96: (0, 1), 128: (0, 1), 192: (0,), 256: (0, 1)}
 
 KERNEL_KINDS = ("tables", "zpass", "ypass", "xpass", "density", "reduce")
 
@@ -89,6 +95,16 @@ def load() -> ctypes.CDLL:
             "pft_profile_end": (i32, [vp, vp, vp, vp]),
             "pft_copy_probe": (i32, [vp, vp, i64, vp]),
             "pft_adjoint": (i32, [vp, vp, vp, i32, vp, vp, vp, vp]),
+            "pft_batch_create": (i32, [P(pft_params), i32, vp, P(vp)]),
+            "pft_batch_destroy": (None, [vp]),
+            "pft_batch_last_error": (ctypes.c_char_p, [vp]),
+            "pft_batch_evaluate": (i32, [vp, vp, vp, vp, vp, vp, vp]),
+            "pft_batch_cl_steps": (i32, [vp, vp, vp, P(pft_step), i32, vp, i64]),
+            "pft_batch_sync": (i32, [vp]),
+            "pft_autotune": (i32, [i32, vp, i32, vp, vp, vp]),
+            "pft_tune_save": (i32, [ctypes.c_char_p]),
+            "pft_tune_load": (i32, [ctypes.c_char_p]),
+            "pft_set_variant": (i32, [vp, i32, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -236,6 +252,9 @@ class Context:
                                        _field(dH_dwminus, self.shape, "dH_dwminus"),
                                        _opt(dH_dL, (3,), "dH_dL"), _opt(H, (1,), "H")))
 
+    def pft_set_variant(self, axis: int, variant: int):
+        self._check(load().pft_set_variant(self._h, axis, variant))
+
     def pft_profile_begin(self):
         self._check(load().pft_profile_begin(self._h))
 
@@ -288,3 +307,79 @@ def pft_copy_probe(src: torch.Tensor, dst: torch.Tensor):
     st = load().pft_copy_probe(src.data_ptr(), dst.data_ptr(), nbytes, _stream())
     if st != PFT_OK:
         raise PftError(st, "pft_copy_probe failed")
+
+
+class Batch:
+    """Owns a ``pft_batch`` of independent replicas (each its own Params)."""
+
+    def __init__(self, params_list, stream: int | None = None):
+        lib = load()
+        self.params = list(params_list)
+        self.n = len(self.params)
+        self.shapes = [(p.nx, p.ny, p.nz) for p in self.params]
+        arr = (pft_params * self.n)(*[p.c() for p in self.params])
+        handle = ctypes.c_void_p()
+        st = lib.pft_batch_create(arr, self.n, _stream() if stream is None else stream, ctypes.byref(handle))
+        if st != PFT_OK:
+            raise PftError(st, "pft_batch_create failed")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().pft_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != PFT_OK:
+            raise PftError(st, load().pft_batch_last_error(self._h).decode())
+
+    def _ptrs(self, tensors, name):
+        if len(tensors) != self.n:
+            raise ValueError(f"{name}: expected {self.n} tensors")
+        return (ctypes.c_void_p * self.n)(*[_field(t, s, name) for t, s in zip(tensors, self.shapes)])
+
+    def pft_batch_evaluate(self, w_plus, w_minus, phi_a, phi_b, Q, H):
+        self._check(load().pft_batch_evaluate(self._h, self._ptrs(w_plus, "w_plus"), self._ptrs(w_minus, "w_minus"),
+                                              self._ptrs(phi_a, "phi_a"), self._ptrs(phi_b, "phi_b"),
+                                              _field(Q, (self.n,), "Q"), _field(H, (self.n,), "H")))
+
+    def pft_batch_cl_steps(self, w_plus, w_minus, step: pft_step, nsteps: int, log=None):
+        rows = 0 if log is None else log.shape[0]
+        if log is not None:
+            _field(log, (rows, self.n, 2), "log")
+        self._check(load().pft_batch_cl_steps(self._h, self._ptrs(w_plus, "w_plus"), self._ptrs(w_minus, "w_minus"),
+                                              ctypes.byref(step), int(nsteps),
+                                              None if log is None else log.data_ptr(), rows))
+
+    def pft_batch_sync(self):
+        self._check(load().pft_batch_sync(self._h))
+
+
+def pft_autotune(precision: int, sizes):
+    """Time every kernel variant for each axis length; returns
+    ({N: (z variant, strided variant)}, {N: [[z ms x3], [strided ms x3]]})."""
+    import numpy as np
+    sz = np.ascontiguousarray(sizes, dtype=np.int32)
+    ch = np.zeros(2 * len(sz), dtype=np.int32)
+    tm = np.zeros(6 * len(sz))
+    st = load().pft_autotune(precision, sz.ctypes.data, len(sz), _stream(), ch.ctypes.data, tm.ctypes.data)
+    if st != PFT_OK:
+        raise PftError(st, "pft_autotune failed")
+    return ({int(n): (int(ch[2 * i]), int(ch[2 * i + 1])) for i, n in enumerate(sz)},
+            {int(n): tm[6 * i:6 * i + 6].reshape(2, 3).tolist() for i, n in enumerate(sz)})
+
+
+def pft_tune_save(path: str):
+    if load().pft_tune_save(path.encode()) != PFT_OK:
+        raise PftError(PFT_E_INVALID, f"cannot write {path}")
+
+
+def pft_tune_load(path: str):
+    if load().pft_tune_load(path.encode()) != PFT_OK:
+        raise PftError(PFT_E_INVALID, f"cannot read {path}")

@@ -30,6 +30,7 @@ enum { kSchemeRQM4 = 0, kSchemeSplit2 = 1 };
 // ------------------------------------------------------------------ z pass --
 template <typename T>
 struct ZArgs {
+    int skip;         // batched launches: this replica has no work at this position
     int64_t nlines;   // nx * ny lines of nz contiguous points
     cx<T>* U;
     cx<T>* V;
@@ -52,23 +53,23 @@ struct LayZ {
     __device__ __forceinline__ int operator()(int k1, int n2) const { return (l * N1 + k1) * (N2 + 1) + n2; }
 };
 
-template <int N1, int N2>
+// W multiplies the lines (z pass) or columns (strided passes) per workgroup;
+// the tuner picks it per axis length.
+template <int N1, int N2, int W = 1>
 struct ZShape {
-    static constexpr int kLines = (N2 >= 64) ? 1 : 64 / N2;  // lines per workgroup
+    static constexpr int kLines = ((N2 >= 64) ? 1 : 64 / N2) * W;  // lines per workgroup
     static constexpr int kThreads = kLines * N2;
     static constexpr int kLds = (N2 == 1) ? 0 : kLines * N1 * (N2 + 1);  // elements
 };
 
-template <typename T, int N1, int N2>
-__global__ __launch_bounds__((ZShape<N1, N2>::kThreads)) void k_zpass(ZArgs<T> A)
+template <typename T, int N1, int N2, int W>
+__device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T>* sh)
 {
     constexpr int N = N1 * N2;
-    constexpr int LPW = ZShape<N1, N2>::kLines;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
+    constexpr int LPW = ZShape<N1, N2, W>::kLines;
     const int tid = threadIdx.x;
     const int t = tid % N2, l = tid / N2;
-    const int64_t line = (int64_t)blockIdx.x * LPW + l;
+    const int64_t line = (int64_t)bid * LPW + l;
     const bool act = line < A.nlines;
     const int64_t base = line * N + t;
     const LayZ<N1, N2> lay{l};
@@ -145,6 +146,23 @@ __global__ __launch_bounds__((ZShape<N1, N2>::kThreads)) void k_zpass(ZArgs<T> A
     }
 }
 
+template <typename T, int N1, int N2, int W>
+__global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads)) void k_zpass(ZArgs<T> A)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    zpass_body<T, N1, N2, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
+// Batched: blockIdx.y selects a replica whose arguments come from a table.
+template <typename T, int N1, int N2, int W>
+__global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads)) void k_zpass_batch(const ZArgs<T>* __restrict__ descs)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const ZArgs<T> A = descs[blockIdx.y];
+    if (A.skip) return;
+    zpass_body<T, N1, N2, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
 // ------------------------------------------------------ strided (x, y) pass --
 template <typename T>
 struct SOps {
@@ -157,6 +175,7 @@ struct SOps {
 
 template <typename T>
 struct SArgs {
+    int skip;             // batched launches: this replica has no work at this position
     cx<T>* U;
     cx<T>* V;
     int64_t S;            // element stride along the lines
@@ -172,24 +191,22 @@ struct LayS {
     __device__ __forceinline__ int operator()(int k1, int n2) const { return (k1 * N2 + n2) * TC + c; }
 };
 
-template <typename T, int N2>
+template <typename T, int N2, int W = 1>
 struct SShape {
     // columns per workgroup: at least one 128-byte row segment, at least one wavefront
     static constexpr int kMinCols = 128 / int(sizeof(cx<T>));
-    static constexpr int kCols = (64 / N2 > kMinCols) ? 64 / N2 : kMinCols;
+    static constexpr int kCols = ((64 / N2 > kMinCols) ? 64 / N2 : kMinCols) * W;
     static constexpr int kThreads = kCols * N2;
 };
 
-// AXIS (0 = x, 1 = y) only names the kernel, so profiles tell the passes apart.
-template <typename T, int N1, int N2, int AXIS>
-__global__ __launch_bounds__((SShape<T, N2>::kThreads)) void k_spass(SArgs<T> A)
+// AXIS: 0 = x (field multiplies allowed), 1 = y.
+template <typename T, int N1, int N2, int AXIS, int W>
+__device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T>* sh)
 {
-    constexpr int TC = SShape<T, N2>::kCols;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    cx<T>* sh = reinterpret_cast<cx<T>*>(smem_raw);
+    constexpr int TC = SShape<T, N2, W>::kCols;
     const int tid = threadIdx.x;
     const int c = tid % TC, t = tid / TC;
-    const int slab = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
+    const int slab = bid / A.ntiles, tile = bid % A.ntiles;
     const int col = tile * TC + c;
     const bool act = col < A.ncols;
     const int64_t base = (int64_t)slab * A.slab_stride + col + (int64_t)t * A.S;
@@ -240,6 +257,23 @@ __global__ __launch_bounds__((SShape<T, N2>::kThreads)) void k_spass(SArgs<T> A)
     }
 }
 
+// AXIS (0 = x, 1 = y) also names the kernel, so profiles tell the passes apart.
+template <typename T, int N1, int N2, int AXIS, int W>
+__global__ __launch_bounds__((SShape<T, N2, W>::kThreads)) void k_spass(SArgs<T> A)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    spass_body<T, N1, N2, AXIS, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
+template <typename T, int N1, int N2, int AXIS, int W>
+__global__ __launch_bounds__((SShape<T, N2, W>::kThreads)) void k_spass_batch(const SArgs<T>* __restrict__ descs)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const SArgs<T> A = descs[blockIdx.y];
+    if (A.skip) return;
+    spass_body<T, N1, N2, AXIS, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
 // ------------------------------------------------------------ launchers ----
 // Axis lengths with a kernel, as (N, N1, N2): N1 points per lane, N2 lanes per line.
 #define PFT_AXIS_SIZES(X) \
@@ -258,6 +292,55 @@ __global__ __launch_bounds__((SShape<T, N2>::kThreads)) void k_spass(SArgs<T> A)
     X(192, 24, 8)         \
     X(256, 16, 16)
 
+// Kernel variants per axis length, as (N, variant, N1, N2, W): variant 0 is the
+// default split and tile; the others widen the workgroup tile (W = 2) or use
+// another radix split N = N1 * N2.  Variant 0 compiles with the rest of the
+// library; the others sit in their own translation units.
+#define PFT_AXIS_VARIANTS0(X) \
+    X(8, 0, 8, 1, 1)          \
+    X(12, 0, 12, 1, 1)        \
+    X(16, 0, 16, 1, 1)        \
+    X(20, 0, 20, 1, 1)        \
+    X(24, 0, 12, 2, 1)        \
+    X(32, 0, 16, 2, 1)        \
+    X(40, 0, 20, 2, 1)        \
+    X(48, 0, 12, 4, 1)        \
+    X(64, 0, 16, 4, 1)        \
+    X(80, 0, 20, 4, 1)        \
+    X(96, 0, 24, 4, 1)        \
+    X(128, 0, 16, 8, 1)       \
+    X(192, 0, 24, 8, 1)       \
+    X(256, 0, 16, 16, 1)
+#define PFT_AXIS_VARIANTS_ALT(X) \
+    X(16, 1, 16, 1, 2)           \
+    X(16, 2, 4, 4, 1)            \
+    X(24, 1, 12, 2, 2)           \
+    X(32, 1, 16, 2, 2)           \
+    X(32, 2, 8, 4, 1)            \
+    X(40, 1, 20, 2, 2)           \
+    X(48, 1, 12, 4, 2)           \
+    X(64, 1, 16, 4, 2)           \
+    X(64, 2, 8, 8, 1)            \
+    X(96, 1, 24, 4, 2)           \
+    X(128, 1, 16, 8, 2)          \
+    X(256, 1, 16, 16, 2)
+#define PFT_AXIS_VARIANTS(X) PFT_AXIS_VARIANTS0(X) PFT_AXIS_VARIANTS_ALT(X)
+
+// Shape of variant v of axis length n; false if there is none.
+inline bool axis_variant(int n, int v, int* n1, int* n2, int* w)
+{
+#define PFT_CASE(N, VID, A1, A2, WW)  \
+    if (n == N && v == VID) {         \
+        *n1 = A1;                     \
+        *n2 = A2;                     \
+        *w = WW;                      \
+        return true;                  \
+    }
+    PFT_AXIS_VARIANTS(PFT_CASE)
+#undef PFT_CASE
+    return false;
+}
+
 inline bool axis_supported(int n)
 {
     switch (n) {
@@ -270,10 +353,78 @@ inline bool axis_supported(int n)
     }
 }
 
-template <typename T>
-hipError_t launch_zpass(int nz, const ZArgs<T>& a, hipStream_t s);
+// Launchers of one group of variants (default ones in namespace v0, the
+// alternatives in namespace alt, each its own translation unit).  The
+// strided launchers set ntiles from the variant's tile width.
+#define PFT_DECLARE_LAUNCHERS(NS)                                                                        \
+    namespace NS {                                                                                     \
+    template <typename T>                                                                              \
+    hipError_t launch_zpass(int nz, int var, const ZArgs<T>& a, hipStream_t s);                        \
+    template <typename T>                                                                              \
+    hipError_t launch_spass(int axis, int n, int var, int64_t ncols, SArgs<T> a, int nslabs, hipStream_t s); \
+    template <typename T>                                                                              \
+    hipError_t launch_zpass_batch(int nz, int var, int64_t nlines, const ZArgs<T>* descs, int nrep,    \
+                                  hipStream_t s);                                                      \
+    template <typename T>                                                                              \
+    hipError_t launch_spass_batch(int axis, int n, int var, int64_t ncols, int nslabs, const SArgs<T>* descs, \
+                                  int nrep, hipStream_t s);                                            \
+    }
+PFT_DECLARE_LAUNCHERS(v0)
+PFT_DECLARE_LAUNCHERS(alt)
+#undef PFT_DECLARE_LAUNCHERS
 
+// `var` selects the kernel variant of the axis length (0 = default).
 template <typename T>
-hipError_t launch_spass(int axis, int n, int64_t ncols_total, SArgs<T> a, int nslabs, hipStream_t s);
+inline hipError_t launch_zpass(int nz, int var, const ZArgs<T>& a, hipStream_t s)
+{
+    return var == 0 ? v0::launch_zpass<T>(nz, 0, a, s) : alt::launch_zpass<T>(nz, var, a, s);
+}
+template <typename T>
+inline hipError_t launch_spass(int axis, int n, int var, int64_t ncols, SArgs<T> a, int nslabs, hipStream_t s)
+{
+    return var == 0 ? v0::launch_spass<T>(axis, n, 0, ncols, a, nslabs, s)
+                    : alt::launch_spass<T>(axis, n, var, ncols, a, nslabs, s);
+}
+// Batched launches over `nrep` replicas of one grid (descs: device table of
+// nrep argument sets, whose ntiles must match spass_tiles for the variant).
+template <typename T>
+inline hipError_t launch_zpass_batch(int nz, int var, int64_t nlines, const ZArgs<T>* descs, int nrep, hipStream_t s)
+{
+    return var == 0 ? v0::launch_zpass_batch<T>(nz, 0, nlines, descs, nrep, s)
+                    : alt::launch_zpass_batch<T>(nz, var, nlines, descs, nrep, s);
+}
+template <typename T>
+inline hipError_t launch_spass_batch(int axis, int n, int var, int64_t ncols, int nslabs, const SArgs<T>* descs,
+                                     int nrep, hipStream_t s)
+{
+    return var == 0 ? v0::launch_spass_batch<T>(axis, n, 0, ncols, nslabs, descs, nrep, s)
+                    : alt::launch_spass_batch<T>(axis, n, var, ncols, nslabs, descs, nrep, s);
+}
+
+// Lanes per line (N2) of an axis length with a kernel, 0 otherwise.
+inline int axis_lanes(int n)
+{
+    switch (n) {
+#define PFT_CASE(N, N1, N2) \
+    case N:                 \
+        return N2;
+        PFT_AXIS_SIZES(PFT_CASE)
+#undef PFT_CASE
+    default:
+        return 0;
+    }
+}
+
+// Column tiles of a strided pass over ncols columns (matches SShape), which
+// the batched argument tables must carry.
+template <typename T>
+inline int spass_tiles(int n, int var, int64_t ncols)
+{
+    int n1 = 0, n2 = 0, w = 0;
+    if (!axis_variant(n, var, &n1, &n2, &w)) return 0;
+    const int minc = 128 / int(sizeof(cx<T>));
+    const int cols = ((64 / n2 > minc) ? 64 / n2 : minc) * w;
+    return (int)((ncols + cols - 1) / cols);
+}
 
 }  // namespace pft

@@ -1,7 +1,13 @@
-// Axis-pass kernels in complex single precision.
+// Default axis-pass kernels in complex float precision.
+#define PFT_VARIANT_LIST PFT_AXIS_VARIANTS0
+#define PFT_VARIANT_NS v0
 #include "passes.inc"
 
 namespace pft {
-template hipError_t launch_zpass<float>(int, const ZArgs<float>&, hipStream_t);
-template hipError_t launch_spass<float>(int, int, int64_t, SArgs<float>, int, hipStream_t);
+namespace v0 {
+template hipError_t launch_zpass<float>(int, int, const ZArgs<float>&, hipStream_t);
+template hipError_t launch_spass<float>(int, int, int, int64_t, SArgs<float>, int, hipStream_t);
+template hipError_t launch_zpass_batch<float>(int, int, int64_t, const ZArgs<float>*, int, hipStream_t);
+template hipError_t launch_spass_batch<float>(int, int, int, int64_t, int, const SArgs<float>*, int, hipStream_t);
+}  // namespace v0
 }  // namespace pft

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -77,7 +78,7 @@ struct TabDesc {
 };
 
 template <typename T>
-__global__ void k_field_tables(const double2* __restrict__ wp, const double2* __restrict__ wm, int64_t M,
+__device__ __forceinline__ void field_tables_body(const double2* __restrict__ wp, const double2* __restrict__ wm, int64_t M,
                                TabDesc d, cx<T>* __restrict__ out)
 {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
@@ -96,6 +97,13 @@ __global__ void k_field_tables(const double2* __restrict__ wp, const double2* __
 }
 
 template <typename T>
+__global__ void k_field_tables(const double2* __restrict__ wp, const double2* __restrict__ wm, int64_t M,
+                               TabDesc d, cx<T>* __restrict__ out)
+{
+    field_tables_body<T>(wp, wm, M, d, out);
+}
+
+template <typename T>
 __global__ void k_to_work(const double2* __restrict__ in, cx<T>* __restrict__ out, int64_t M)
 {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x)
@@ -111,7 +119,7 @@ __global__ void k_from_work(const cx<T>* __restrict__ in, double2* __restrict__ 
 
 // Partial sums (one per block) of a complex array, compensated.
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_sum_partials(const cx<T>* __restrict__ x, int64_t n,
+__device__ __forceinline__ void sum_partials_body(const cx<T>* __restrict__ x, int64_t n,
                                                               double2* __restrict__ partials)
 {
     __shared__ double2 sh[kRedThreads];
@@ -122,6 +130,13 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_partials(const cx<T>* __res
     }
     const double2 s = block_sum(make_double2(re.value(), im.value()), sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_sum_partials(const cx<T>* __restrict__ x, int64_t n,
+                                                              double2* __restrict__ partials)
+{
+    sum_partials_body<T>(x, n, partials);
 }
 
 // Per-node sums of q_j * qd_{K-j}: blockIdx.y is the node.
@@ -146,7 +161,7 @@ __global__ __launch_bounds__(kRedThreads) void k_nodeq_partials(const cx<T>* __r
 
 // Final reduction of nrows rows of np partials each: out[r] = scale * sum.
 // Optionally flags a non-finite result (bit 0) and mirrors row 0 to out2.
-__global__ __launch_bounds__(kRedThreads) void k_final_sum(const double2* __restrict__ partials, int np,
+__device__ __forceinline__ void final_sum_body(const double2* __restrict__ partials, int np,
                                                            double scale, double2* __restrict__ out,
                                                            double2* __restrict__ out2, uint32_t* flags)
 {
@@ -166,12 +181,19 @@ __global__ __launch_bounds__(kRedThreads) void k_final_sum(const double2* __rest
     }
 }
 
+__global__ __launch_bounds__(kRedThreads) void k_final_sum(const double2* __restrict__ partials, int np,
+                                                           double scale, double2* __restrict__ out,
+                                                           double2* __restrict__ out2, uint32_t* flags)
+{
+    final_sum_body(partials, np, scale, out, out2, flags);
+}
+
 // Contour-weighted q * q-dagger reduction (Eq. (8) divided by rho_0):
 // phi_A(x) = (1/Q) sum_{j <= J} tauA_j q_j(x) qd_{K-j}(x), phi_B over j >= J.
 // Per-site compensated double sums; each lane owns one site and streams
 // through the K+1 slices of both stores.
 template <typename T>
-__global__ void k_density(const cx<T>* __restrict__ qs, const cx<T>* __restrict__ qds, int K, int J, int64_t M,
+__device__ __forceinline__ void density_body(const cx<T>* __restrict__ qs, const cx<T>* __restrict__ qds, int K, int J, int64_t M,
                           const double* __restrict__ tau, const double2* __restrict__ Qp,
                           double2* __restrict__ phiA, double2* __restrict__ phiB, double2* __restrict__ Qout)
 {
@@ -199,8 +221,16 @@ __global__ void k_density(const cx<T>* __restrict__ qs, const cx<T>* __restrict_
     }
 }
 
+template <typename T>
+__global__ void k_density(const cx<T>* __restrict__ qs, const cx<T>* __restrict__ qds, int K, int J, int64_t M,
+                          const double* __restrict__ tau, const double2* __restrict__ Qp,
+                          double2* __restrict__ phiA, double2* __restrict__ phiB, double2* __restrict__ Qout)
+{
+    density_body<T>(qs, qds, K, J, M, tau, Qp, phiA, phiB, Qout);
+}
+
 // Partial sums of w_-^2 / chiN - i w_+ (the local part of Eq. (3)).
-__global__ __launch_bounds__(kRedThreads) void k_ham_partials(const double2* __restrict__ wp,
+__device__ __forceinline__ void ham_partials_body(const double2* __restrict__ wp,
                                                               const double2* __restrict__ wm, int64_t M,
                                                               double inv_chiN, double2* __restrict__ partials)
 {
@@ -216,8 +246,15 @@ __global__ __launch_bounds__(kRedThreads) void k_ham_partials(const double2* __r
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+__global__ __launch_bounds__(kRedThreads) void k_ham_partials(const double2* __restrict__ wp,
+                                                              const double2* __restrict__ wm, int64_t M,
+                                                              double inv_chiN, double2* __restrict__ partials)
+{
+    ham_partials_body(wp, wm, M, inv_chiN, partials);
+}
+
 // H = C dV S - C V Log Q (principal branch), h = H / (C V).
-__global__ __launch_bounds__(kRedThreads) void k_ham_final(const double2* __restrict__ partials, int np, double C,
+__device__ __forceinline__ void ham_final_body(const double2* __restrict__ partials, int np, double C,
                                                            double dV, double V, const double2* __restrict__ Qp,
                                                            double2* __restrict__ H, double2* __restrict__ hint,
                                                            double2* __restrict__ Sout)
@@ -238,6 +275,14 @@ __global__ __launch_bounds__(kRedThreads) void k_ham_final(const double2* __rest
         if (hint) *hint = make_double2(h.x / (C * V), h.y / (C * V));
         if (Sout) *Sout = s;
     }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_ham_final(const double2* __restrict__ partials, int np, double C,
+                                                           double dV, double V, const double2* __restrict__ Qp,
+                                                           double2* __restrict__ H, double2* __restrict__ hint,
+                                                           double2* __restrict__ Sout)
+{
+    ham_final_body(partials, np, C, dV, V, Qp, H, hint, Sout);
 }
 
 // ------------------------------------------------------------ Philox noise --
@@ -317,7 +362,7 @@ struct UpdArgs {
     uint64_t seed, rep, step;
 };
 
-__global__ void k_update(UpdArgs a)
+__device__ __forceinline__ void update_body(UpdArgs a)
 {
     const int64_t ng = (a.M + 3) / 4;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (int64_t)gridDim.x * blockDim.x) {
@@ -337,6 +382,11 @@ __global__ void k_update(UpdArgs a)
             a.wm[x] = make_double2(m.x - a.dtm * Fm.x + a.sm * zm[r], m.y - a.dtm * Fm.y);
         }
     }
+}
+
+__global__ void k_update(UpdArgs a)
+{
+    update_body(a);
 }
 
 // ------------------------------------------------------------ reverse mode --
@@ -515,6 +565,134 @@ __global__ void k_copy(const cx<T>* __restrict__ src, cx<T>* __restrict__ d0, cx
     }
 }
 
+// ---------------------------------------------------------------- batches --
+// Job-table versions of the small kernels: blockIdx.y selects a replica,
+// whose arguments are read from a device table.
+template <typename T>
+struct TabJob {
+    const double2* wp;
+    const double2* wm;
+    int64_t M;
+    TabDesc d;
+    cx<T>* out;
+};
+template <typename T>
+struct SumJob {
+    const cx<T>* x;
+    int64_t n;
+    double2* partials;
+};
+struct FinJob {
+    const double2* partials;
+    int np;
+    double scale;
+    double2* out;
+    uint32_t* flags;
+};
+template <typename T>
+struct DensJob {
+    const cx<T>* qs;
+    const cx<T>* qds;
+    int K, J;
+    int64_t M;
+    const double* tau;
+    const double2* Qp;
+    double2* phiA;
+    double2* phiB;
+    double2* Qout;
+};
+struct HamJob {
+    const double2* wp;
+    const double2* wm;
+    int64_t M;
+    double inv_chiN;
+    double2* partials;
+    int np;
+    double C, dV, V;
+    const double2* Qp;
+    double2* H;
+    double2* hint;
+    double2* Sout;
+};
+struct LogJob {
+    const double2* Q;
+    const double2* H;
+};
+
+template <typename T>
+__global__ void k_tables_batch(const TabJob<T>* __restrict__ jobs)
+{
+    const TabJob<T> a = jobs[blockIdx.y];
+    field_tables_body<T>(a.wp, a.wm, a.M, a.d, a.out);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_sum_partials_batch(const SumJob<T>* __restrict__ jobs)
+{
+    const SumJob<T> a = jobs[blockIdx.y];
+    sum_partials_body<T>(a.x, a.n, a.partials);
+}
+
+// grid (1, replicas): final_sum_body reduces row blockIdx.x = 0 of each job
+__global__ __launch_bounds__(kRedThreads) void k_final_batch(const FinJob* __restrict__ jobs)
+{
+    const FinJob a = jobs[blockIdx.y];
+    final_sum_body(a.partials, a.np, a.scale, a.out, (double2*)nullptr, a.flags);
+}
+
+template <typename T>
+__global__ void k_density_batch(const DensJob<T>* __restrict__ jobs)
+{
+    const DensJob<T> a = jobs[blockIdx.y];
+    density_body<T>(a.qs, a.qds, a.K, a.J, a.M, a.tau, a.Qp, a.phiA, a.phiB, a.Qout);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_ham_partials_batch(const HamJob* __restrict__ jobs)
+{
+    const HamJob a = jobs[blockIdx.y];
+    ham_partials_body(a.wp, a.wm, a.M, a.inv_chiN, a.partials);
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_ham_final_batch(const HamJob* __restrict__ jobs)
+{
+    const HamJob a = jobs[blockIdx.y];
+    ham_final_body(a.partials, a.np, a.C, a.dV, a.V, a.Qp, a.H, a.hint, a.Sout);
+}
+
+// The Langevin step index comes from device memory so one captured graph
+// serves every step.
+__global__ void k_update_batch(const UpdArgs* __restrict__ jobs, const uint64_t* __restrict__ step)
+{
+    UpdArgs a = jobs[blockIdx.y];
+    a.step += *step;
+    update_body(a);
+}
+
+// Q and H of every replica at log row *row (if below capacity).
+__global__ void k_batch_log(const LogJob* __restrict__ jobs, int n, double2* __restrict__ log,
+                            const uint64_t* __restrict__ row, uint64_t capacity)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = *row;
+    if (r < n && i < capacity) {
+        log[(i * n + r) * 2] = *jobs[r].Q;
+        log[(i * n + r) * 2 + 1] = *jobs[r].H;
+    }
+}
+
+__global__ void k_batch_advance(uint64_t* __restrict__ step, uint64_t* __restrict__ row)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *step += 1;
+        *row += 1;
+    }
+}
+
+__global__ void k_set_u64(uint64_t* __restrict__ p, uint64_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 // Plain streaming copy (16 bytes per lane per iteration).
 __global__ void k_copy_probe(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n)
 {
@@ -569,6 +747,21 @@ int contour_plan(int ns, double f, double* h, int* blk, int* junction)
 
 }  // namespace
 
+namespace {
+// Kernel variant per (precision, axis length, kind: 0 = z pass, 1 = strided
+// passes), used by contexts created afterwards; filled by pft_autotune or
+// pft_tune_load (also from $PFT_TUNE_CACHE on the first pft_create).
+int g_tune[2][257][2] = {};
+bool g_tune_env_checked = false;
+
+int tuned_variant(int prec, int n, int kind)
+{
+    int n1, n2, w;
+    const int v = (n >= 0 && n <= 256) ? g_tune[prec & 1][n][kind] : 0;
+    return pft::axis_variant(n, v, &n1, &n2, &w) ? v : 0;
+}
+}  // namespace
+
 struct pft_ctx {
     pft_params p{};
     hipStream_t stream = nullptr;
@@ -579,6 +772,7 @@ struct pft_ctx {
     std::vector<int> blk, kind, hid;  // per step: E table kind (0..3), step-length id (0..2)
     double hval[3] = {0, 0, 0};       // ds, A junction sub-step, B junction sub-step
     int maxN = 0;
+    int var[3] = {0, 0, 0};           // kernel variant of each axis pass (x, y, z)
     size_t elem = 0;                  // bytes per propagator value
     // device buffers
     void* qs = nullptr;
@@ -724,7 +918,7 @@ pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout, 
     if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
     if (hcap) bytes += E;
     ProfScope ps(c, PFT_K_ZPASS, bytes);
-    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, a, c->stream));
+    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], a, c->stream));
     return PFT_OK;
 }
 
@@ -748,11 +942,11 @@ pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV, const
     if (axis == 0) {
         a.S = nynz;
         a.slab_stride = 0;
-        PFT_HIP(c, pft::launch_spass<T>(0, c->p.nx, nynz, a, 1, c->stream));
+        PFT_HIP(c, pft::launch_spass<T>(0, c->p.nx, c->var[0], nynz, a, 1, c->stream));
     } else {
         a.S = c->p.nz;
         a.slab_stride = nynz;
-        PFT_HIP(c, pft::launch_spass<T>(1, c->p.ny, c->p.nz, a, c->p.nx, c->stream));
+        PFT_HIP(c, pft::launch_spass<T>(1, c->p.ny, c->var[1], c->p.nz, a, c->p.nx, c->stream));
     }
     return PFT_OK;
 }
@@ -977,7 +1171,7 @@ pft_status diffuse_t(pft_ctx* c, double* u, double h)
     a.has_next = 1;
     a.gh_n = gptr<T>(c, 3, 0, 2);
     a.gf_n = gptr<T>(c, 3, 1, 2);
-    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, a, c->stream));
+    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], a, c->stream));
     const pft::SOps<T> none{nullptr, nullptr, nullptr};
     s = spass<T>(c, 1, none, {gptr<T>(c, 3, 1, 1), nullptr, nullptr});
     if (s) return s;
@@ -1111,7 +1305,7 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
                 z.scheme = PFT_SPLIT2;
                 z.has_next = 1;
                 z.gf_n = dtab(2);
-                PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, z, c->stream));
+                PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], z, c->stream));
                 hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(M, 256)), dim3(256), 0, c->stream, X[xi], S[xi * 3 + 1],
                                    S[xi * 3 + 0], M);
                 PFT_HIP(c, hipGetLastError());
@@ -1159,6 +1353,79 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     return PFT_OK;
 }
 
+// Argument sets of the passes, built without launching (the batched tables
+// hold one per replica and sweep position).
+template <typename T>
+pft::ZArgs<T> zargs(const pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout)
+{
+    pft::ZArgs<T> a{};
+    a.nlines = (int64_t)c->p.nx * c->p.ny;
+    a.U = static_cast<cx<T>*>(c->U);
+    a.V = static_cast<cx<T>*>(c->V);
+    a.qin = qin;
+    a.qout = qout;
+    a.scheme = c->p.scheme;
+    a.has_prev = prev >= 0;
+    a.has_next = next >= 0;
+    if (prev >= 0) {
+        a.Ep = etab<T>(c, c->kind[prev]);
+        a.gh_p = gptr<T>(c, c->hid[prev], 0, 2);
+    }
+    if (next >= 0) {
+        a.En = etab<T>(c, c->kind[next]);
+        a.gh_n = gptr<T>(c, c->hid[next], 0, 2);
+        a.gf_n = gptr<T>(c, c->hid[next], 1, 2);
+    }
+    return a;
+}
+
+template <typename T>
+pft::SArgs<T> sargs(const pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV)
+{
+    pft::SArgs<T> a{};
+    a.U = static_cast<cx<T>*>(c->U);
+    a.V = static_cast<cx<T>*>(c->V);
+    a.opU = opU;
+    a.opV = opV;
+    const int64_t nynz = (int64_t)c->p.ny * c->p.nz;
+    if (axis == 0) {
+        a.S = nynz;
+        a.slab_stride = 0;
+        a.ncols = (int)nynz;
+        a.ntiles = pft::spass_tiles<T>(c->p.nx, c->var[0], nynz);
+    } else {
+        a.S = c->p.nz;
+        a.slab_stride = nynz;
+        a.ncols = c->p.nz;
+        a.ntiles = pft::spass_tiles<T>(c->p.ny, c->var[1], c->p.nz);
+    }
+    return a;
+}
+
+// The strided passes of step j, in order (three for the Richardson step,
+// two for the plain split), as in step_body.
+template <typename T>
+int body_passes(const pft_ctx* c, int j, int axis[3], pft::SArgs<T> out[3])
+{
+    const int hd = c->hid[j];
+    const cx<T>* e = etab<T>(c, c->kind[j]);
+    const pft::SOps<T> none{nullptr, nullptr, nullptr};
+    if (c->p.scheme == PFT_RQM4) {
+        axis[0] = 1;
+        out[0] = sargs<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, {gptr<T>(c, hd, 1, 1), nullptr, nullptr});
+        axis[1] = 0;
+        out[1] = sargs<T>(c, 0, {gptr<T>(c, hd, 0, 0), e, gptr<T>(c, hd, 0, 0)}, {gptr<T>(c, hd, 1, 0), e, nullptr});
+        axis[2] = 1;
+        out[2] = sargs<T>(c, 1, {gptr<T>(c, hd, 0, 1), nullptr, nullptr}, none);
+        return 3;
+    }
+    axis[0] = 1;
+    out[0] = sargs<T>(c, 1, none, {gptr<T>(c, hd, 1, 1), nullptr, nullptr});
+    axis[1] = 0;
+    out[1] = sargs<T>(c, 0, none, {gptr<T>(c, hd, 1, 0), nullptr, nullptr});
+    return 2;
+}
+
 void free_all(pft_ctx* c)
 {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -1168,6 +1435,430 @@ void free_all(pft_ctx* c)
                     c->adjAcc};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+}
+
+}  // namespace
+
+
+// ================================================================ batches ==
+// Many independent replicas (uneven grids, contour step counts, f, chi N) run
+// together: replicas are grouped by grid shape; every pass of a group is one
+// launch over all its replicas, whose arguments for each sweep position come
+// from device tables built once; groups run on their own streams; one field
+// step of the whole batch is captured into a HIP graph and replayed.
+namespace {
+
+struct BatchGroup {
+    int nx = 0, ny = 0, nz = 0;
+    std::vector<int> reps;
+    int maxK = 0;
+    int64_t maxM = 0;
+    int npass = 0;               // strided passes per step (3 or 2)
+    int sp_axis[3] = {0, 0, 0};
+    int var[3] = {0, 0, 0};      // kernel variants (x, y, z) of the group's grid
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
+    void* zd = nullptr;          // [dir 2][pos maxK+1][R] ZArgs
+    void* sd = nullptr;          // [dir 2][pos maxK][npass][R] SArgs
+    void* jobs = nullptr;        // job tables for the small kernels
+    size_t off_tab = 0, off_sum = 0, off_fin = 0, off_dens = 0, off_ham = 0, off_upd = 0;
+};
+
+}  // namespace
+
+struct pft_batch {
+    int n = 0;
+    int precision = 0, scheme = 0;
+    hipStream_t stream = nullptr;  // the caller's stream
+    hipStream_t own = nullptr;     // the batch's stream: work is captured and replayed here
+    std::vector<pft_ctx*> ctx;
+    std::vector<BatchGroup> groups;
+    hipEvent_t fork = nullptr;
+    hipEvent_t in = nullptr, out = nullptr;  // joins with the caller's stream
+    uint64_t* counters = nullptr;  // [0] Langevin step, [1] log row
+    LogJob* logj = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const double*> gwp, gwm;  // field pointers baked into the graph
+    pft_step gst{};
+    double* glog = nullptr;
+    int64_t gcap = 0;
+    std::string err;
+
+    pft_status fail(pft_status s, const char* fmt, ...)
+    {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        std::vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return s;
+    }
+};
+
+namespace {
+
+#define PFT_BHIP(b, call)                                                                              \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return (b)->fail(PFT_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_));             \
+    } while (0)
+
+void batch_free(pft_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (BatchGroup& g : b->groups) {
+        if (g.s) (void)hipStreamDestroy(g.s);
+        if (g.done) (void)hipEventDestroy(g.done);
+        if (g.zd) (void)hipFree(g.zd);
+        if (g.sd) (void)hipFree(g.sd);
+        if (g.jobs) (void)hipFree(g.jobs);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->in) (void)hipEventDestroy(b->in);
+    if (b->out) (void)hipEventDestroy(b->out);
+    if (b->own) (void)hipStreamDestroy(b->own);
+    if (b->counters) (void)hipFree(b->counters);
+    if (b->logj) (void)hipFree(b->logj);
+    for (pft_ctx* c : b->ctx) pft_destroy(c);
+}
+
+// Argument tables of the passes of one group, for both sweeps and every
+// sweep position; a replica whose K is exhausted is marked skip.
+template <typename T>
+pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
+{
+    const int R = (int)g.reps.size();
+    std::vector<pft::ZArgs<T>> zd((size_t)2 * (g.maxK + 1) * R);
+    std::vector<pft::SArgs<T>> sd((size_t)2 * g.maxK * g.npass * R);
+    for (int dir = 0; dir < 2; ++dir)
+        for (int ri = 0; ri < R; ++ri) {
+            pft_ctx* c = b->ctx[g.reps[ri]];
+            const int K = c->K;
+            auto stepj = [&](int i) { return dir ? K - 1 - i : i; };
+            void* store = dir ? c->qds : c->qs;
+            for (int p = 0; p <= g.maxK; ++p) {
+                const int i = p - 1;  // Z at position p completes step i and starts step i + 1
+                pft::ZArgs<T>& z = zd[((size_t)dir * (g.maxK + 1) + p) * R + ri];
+                if (i >= K) {
+                    z.skip = 1;
+                    continue;
+                }
+                z = zargs<T>(c, i >= 0 ? stepj(i) : -1, i + 1 < K ? stepj(i + 1) : -1, nullptr,
+                             slice<T>(store, c, i + 1));
+            }
+            for (int p = 0; p < g.maxK; ++p) {
+                int ax[3];
+                pft::SArgs<T> sa[3];
+                if (p < K) body_passes<T>(c, stepj(p), ax, sa);
+                for (int k = 0; k < g.npass; ++k) {
+                    pft::SArgs<T>& d = sd[(((size_t)dir * g.maxK + p) * g.npass + k) * R + ri];
+                    if (p >= K) {
+                        d.skip = 1;
+                        continue;
+                    }
+                    d = sa[k];
+                }
+            }
+        }
+    PFT_BHIP(b, hipMalloc(&g.zd, zd.size() * sizeof(zd[0])));
+    PFT_BHIP(b, hipMalloc(&g.sd, std::max<size_t>(1, sd.size()) * sizeof(pft::SArgs<T>)));
+    PFT_BHIP(b, hipMemcpy(g.zd, zd.data(), zd.size() * sizeof(zd[0]), hipMemcpyHostToDevice));
+    if (!sd.empty()) PFT_BHIP(b, hipMemcpy(g.sd, sd.data(), sd.size() * sizeof(sd[0]), hipMemcpyHostToDevice));
+    return PFT_OK;
+}
+
+// Job tables of the small kernels of one group for the given field pointers
+// and outputs (phi / Q / H default to each context's internal buffers).
+template <typename T>
+pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp, const double* const* wm,
+                            double* const* phia, double* const* phib, double* Qout, double* Hout, const pft_step* st)
+{
+    const int R = (int)g.reps.size();
+    std::vector<TabJob<T>> tab(R);
+    std::vector<SumJob<T>> sum(R);
+    std::vector<FinJob> fin(R);
+    std::vector<DensJob<T>> dens(R);
+    std::vector<HamJob> ham(R);
+    std::vector<UpdArgs> upd(R);
+    constexpr int kQParts = 64;
+    for (int ri = 0; ri < R; ++ri) {
+        const int r = g.reps[ri];
+        pft_ctx* c = b->ctx[r];
+        TabDesc d{};
+        d.n = c->K == c->p.ns ? 2 : 4;
+        d.blk[0] = 0; d.a[0] = c->hval[0] / 4;
+        d.blk[1] = 1; d.a[1] = c->hval[0] / 4;
+        d.blk[2] = 0; d.a[2] = c->hval[1] / 4;
+        d.blk[3] = 1; d.a[3] = c->hval[2] / 4;
+        tab[ri] = {reinterpret_cast<const double2*>(wp[r]), reinterpret_cast<const double2*>(wm[r]), c->M, d,
+                   static_cast<cx<T>*>(c->E)};
+        sum[ri] = {slice<T>(c->qs, c, c->K), c->M, c->partials};
+        fin[ri] = {c->partials, kQParts, 1.0 / (double)c->M, c->scal, c->flags};
+        double2* pa = phia ? reinterpret_cast<double2*>(phia[r]) : c->phi;
+        double2* pb = phib ? reinterpret_cast<double2*>(phib[r]) : c->phi + c->M;
+        dens[ri] = {static_cast<const cx<T>*>(c->qs), static_cast<const cx<T>*>(c->qds), c->K, c->J, c->M, c->tau,
+                    c->scal, pa, pb, Qout ? reinterpret_cast<double2*>(Qout) + r : nullptr};
+        const double V = c->p.lx * c->p.ly * c->p.lz;
+        ham[ri] = {reinterpret_cast<const double2*>(wp[r]), reinterpret_cast<const double2*>(wm[r]), c->M,
+                   1.0 / c->p.chiN, c->partials + kQParts, kQParts, c->p.C, V / (double)c->M, V, c->scal,
+                   Hout ? reinterpret_cast<double2*>(Hout) + r : c->scal + 1, c->scal + 2, c->scal + 4};
+        UpdArgs a{};
+        if (st) {
+            const double dV = V / (double)c->M;
+            a.wp = reinterpret_cast<double2*>(const_cast<double*>(wp[r]));
+            a.wm = reinterpret_cast<double2*>(const_cast<double*>(wm[r]));
+            a.phiA = pa;
+            a.phiB = pb;
+            a.M = c->M;
+            a.two_over_chiN = 2.0 / c->p.chiN;
+            a.dtp = st->lambda_plus * st->dt;
+            a.dtm = st->lambda_minus * st->dt;
+            a.noise = st->noise != 0;
+            a.sp = a.noise ? std::sqrt(2.0 * st->lambda_plus * st->dt / (c->p.C * dV)) : 0.0;
+            a.sm = a.noise ? std::sqrt(2.0 * st->lambda_minus * st->dt / (c->p.C * dV)) : 0.0;
+            a.seed = st->seed;
+            a.rep = st->replica + (uint64_t)r;
+            a.step = 0;  // the device step counter is added at run time
+        }
+        upd[ri] = a;
+    }
+    size_t o = 0;
+    auto place = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) & ~size_t(255);
+        return at;
+    };
+    g.off_tab = place(R * sizeof(TabJob<T>));
+    g.off_sum = place(R * sizeof(SumJob<T>));
+    g.off_fin = place(R * sizeof(FinJob));
+    g.off_dens = place(R * sizeof(DensJob<T>));
+    g.off_ham = place(R * sizeof(HamJob));
+    g.off_upd = place(R * sizeof(UpdArgs));
+    if (!g.jobs) PFT_BHIP(b, hipMalloc(&g.jobs, o));
+    char* base = static_cast<char*>(g.jobs);
+    PFT_BHIP(b, hipMemcpy(base + g.off_tab, tab.data(), R * sizeof(tab[0]), hipMemcpyHostToDevice));
+    PFT_BHIP(b, hipMemcpy(base + g.off_sum, sum.data(), R * sizeof(sum[0]), hipMemcpyHostToDevice));
+    PFT_BHIP(b, hipMemcpy(base + g.off_fin, fin.data(), R * sizeof(fin[0]), hipMemcpyHostToDevice));
+    PFT_BHIP(b, hipMemcpy(base + g.off_dens, dens.data(), R * sizeof(dens[0]), hipMemcpyHostToDevice));
+    PFT_BHIP(b, hipMemcpy(base + g.off_ham, ham.data(), R * sizeof(ham[0]), hipMemcpyHostToDevice));
+    PFT_BHIP(b, hipMemcpy(base + g.off_upd, upd.data(), R * sizeof(upd[0]), hipMemcpyHostToDevice));
+    return PFT_OK;
+}
+
+// Enqueue one evaluation (and, if update, the field step) of one group on
+// its stream.
+template <typename T>
+pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update)
+{
+    const int R = (int)g.reps.size();
+    hipStream_t s = g.s;
+    char* jb = static_cast<char*>(g.jobs);
+    const int64_t nlines = (int64_t)g.nx * g.ny;
+    hipLaunchKernelGGL((k_tables_batch<T>), dim3(grid_for(g.maxM, 256), R), dim3(256), 0, s,
+                       reinterpret_cast<const TabJob<T>*>(jb + g.off_tab));
+    PFT_BHIP(b, hipGetLastError());
+    const pft::ZArgs<T>* zd = static_cast<const pft::ZArgs<T>*>(g.zd);
+    const pft::SArgs<T>* sd = static_cast<const pft::SArgs<T>*>(g.sd);
+    const int n_ax[2] = {g.nx, g.ny};
+    const int64_t ncols[2] = {(int64_t)g.ny * g.nz, g.nz};
+    const int nslabs[2] = {1, g.nx};
+    for (int dir = 0; dir < 2; ++dir) {
+        PFT_BHIP(b, pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + ((size_t)dir * (g.maxK + 1) + 0) * R, R, s));
+        for (int p = 0; p < g.maxK; ++p) {
+            for (int k = 0; k < g.npass; ++k) {
+                const int ax = g.sp_axis[k];
+                PFT_BHIP(b, pft::launch_spass_batch<T>(ax, n_ax[ax], g.var[ax], ncols[ax], nslabs[ax],
+                                                       sd + (((size_t)dir * g.maxK + p) * g.npass + k) * R, R, s));
+            }
+            PFT_BHIP(b, pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + ((size_t)dir * (g.maxK + 1) + p + 1) * R, R, s));
+        }
+    }
+    hipLaunchKernelGGL((k_sum_partials_batch<T>), dim3(64, R), dim3(kRedThreads), 0, s,
+                       reinterpret_cast<const SumJob<T>*>(jb + g.off_sum));
+    hipLaunchKernelGGL(k_final_batch, dim3(1, R), dim3(kRedThreads), 0, s, reinterpret_cast<const FinJob*>(jb + g.off_fin));
+    hipLaunchKernelGGL((k_density_batch<T>), dim3(grid_for(g.maxM, 256), R), dim3(256), 0, s,
+                       reinterpret_cast<const DensJob<T>*>(jb + g.off_dens));
+    hipLaunchKernelGGL(k_ham_partials_batch, dim3(64, R), dim3(kRedThreads), 0, s,
+                       reinterpret_cast<const HamJob*>(jb + g.off_ham));
+    hipLaunchKernelGGL(k_ham_final_batch, dim3(1, R), dim3(kRedThreads), 0, s,
+                       reinterpret_cast<const HamJob*>(jb + g.off_ham));
+    if (update)
+        hipLaunchKernelGGL(k_update_batch, dim3(grid_for((g.maxM + 3) / 4, 256), R), dim3(256), 0, s,
+                           reinterpret_cast<const UpdArgs*>(jb + g.off_upd), b->counters);
+    PFT_BHIP(b, hipGetLastError());
+    return PFT_OK;
+}
+
+// Fork the group streams off the batch stream, enqueue every group, join.
+template <typename T>
+pft_status batch_enqueue(pft_batch* b, bool update, const double2* logbuf, int64_t cap)
+{
+    PFT_BHIP(b, hipEventRecord(b->fork, b->own));
+    for (BatchGroup& g : b->groups) {
+        PFT_BHIP(b, hipStreamWaitEvent(g.s, b->fork, 0));
+        pft_status st = batch_enqueue_group<T>(b, g, update);
+        if (st) return st;
+        PFT_BHIP(b, hipEventRecord(g.done, g.s));
+        PFT_BHIP(b, hipStreamWaitEvent(b->own, g.done, 0));
+    }
+    if (update) {
+        if (logbuf)
+            hipLaunchKernelGGL(k_batch_log, dim3((b->n + 255) / 256), dim3(256), 0, b->own, b->logj, b->n,
+                               const_cast<double2*>(logbuf), b->counters + 1, (uint64_t)cap);
+        hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, b->own, b->counters, b->counters + 1);
+        PFT_BHIP(b, hipGetLastError());
+    }
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status batch_setup_t(pft_batch* b)
+{
+    for (BatchGroup& g : b->groups) {
+        pft_status s = batch_build_pass_tables<T>(b, g);
+        if (s) return s;
+    }
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status batch_evaluate_t(pft_batch* b, const double* const* wp, const double* const* wm, double* const* pa,
+                            double* const* pb, double* Q, double* H)
+{
+    for (BatchGroup& g : b->groups) {
+        pft_status s = batch_build_jobs<T>(b, g, wp, wm, pa, pb, Q, H, nullptr);
+        if (s) return s;
+    }
+    b->gwp.clear();  // the jobs no longer match a captured graph
+    PFT_BHIP(b, hipEventRecord(b->in, b->stream));
+    PFT_BHIP(b, hipStreamWaitEvent(b->own, b->in, 0));
+    pft_status s = batch_enqueue<T>(b, false, nullptr, 0);
+    if (s) return s;
+    PFT_BHIP(b, hipEventRecord(b->out, b->own));
+    PFT_BHIP(b, hipStreamWaitEvent(b->stream, b->out, 0));
+    return PFT_OK;
+}
+
+template <typename T>
+pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* const* wm, const pft_step* st,
+                         int nsteps, double* log, int64_t cap)
+{
+    const bool same = b->exec && b->gwp.size() == (size_t)b->n &&
+                      std::equal(b->gwp.begin(), b->gwp.end(), wp) && std::equal(b->gwm.begin(), b->gwm.end(), wm) &&
+                      b->glog == log && b->gcap == cap && b->gst.dt == st->dt &&
+                      b->gst.lambda_plus == st->lambda_plus && b->gst.lambda_minus == st->lambda_minus &&
+                      b->gst.seed == st->seed && b->gst.replica == st->replica && b->gst.noise == st->noise;
+    if (!same) {
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        for (BatchGroup& g : b->groups) {
+            pft_status s = batch_build_jobs<T>(b, g, wp, wm, nullptr, nullptr, nullptr, nullptr, st);
+            if (s) return s;
+        }
+        std::vector<LogJob> lj(b->n);
+        for (int r = 0; r < b->n; ++r) lj[r] = {b->ctx[r]->scal, b->ctx[r]->scal + 1};
+        PFT_BHIP(b, hipMemcpy(b->logj, lj.data(), lj.size() * sizeof(LogJob), hipMemcpyHostToDevice));
+        PFT_BHIP(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+        pft_status s = batch_enqueue<T>(b, true, reinterpret_cast<const double2*>(log), cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(b->own, &graph);
+        if (s) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (ec != hipSuccess) return b->fail(PFT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        b->graph = graph;
+        PFT_BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->gwp.assign(wp, wp + b->n);
+        b->gwm.assign(wm, wm + b->n);
+        b->glog = log;
+        b->gcap = cap;
+        b->gst = *st;
+    }
+    PFT_BHIP(b, hipEventRecord(b->in, b->stream));
+    PFT_BHIP(b, hipStreamWaitEvent(b->own, b->in, 0));
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, b->own, b->counters, st->step);
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, b->own, b->counters + 1, (uint64_t)0);
+    PFT_BHIP(b, hipGetLastError());
+    for (int i = 0; i < nsteps; ++i) PFT_BHIP(b, hipGraphLaunch(b->exec, b->own));
+    PFT_BHIP(b, hipEventRecord(b->out, b->own));
+    PFT_BHIP(b, hipStreamWaitEvent(b->stream, b->out, 0));
+    return PFT_OK;
+}
+
+}  // namespace
+
+
+// ============================================================== autotuner ==
+namespace {
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+// Side length A of the two other axes of the timing grid (A * A * N <= 4 Mi sites).
+int tune_side(int N)
+{
+    const int sides[] = {256, 192, 128, 96, 64, 48, 32, 24, 16, 8};
+    for (int a : sides)
+        if ((int64_t)a * a * N <= (int64_t)4 << 20) return a;
+    return 8;
+}
+
+// Average duration (ms) of `reps` launches of one pass kind with variant v.
+template <typename T>
+double time_variant(pft_ctx* c, int kind, int v, int reps)
+{
+    cx<T>* w0 = static_cast<cx<T>*>(c->work);
+    auto launch = [&]() -> hipError_t {
+        if (kind == 0) {
+            pft::ZArgs<T> a{};
+            a.nlines = (int64_t)c->p.nx * c->p.ny;
+            a.U = static_cast<cx<T>*>(c->U);
+            a.V = static_cast<cx<T>*>(c->V);
+            a.qin = w0;
+            a.scheme = PFT_SPLIT2;
+            a.has_next = 1;
+            a.gh_n = gptr<T>(c, 0, 0, 2);
+            a.gf_n = gptr<T>(c, 0, 1, 2);
+            return pft::launch_zpass<T>(c->p.nz, v, a, c->stream);
+        }
+        pft::SArgs<T> a{};
+        a.U = static_cast<cx<T>*>(c->U);
+        a.V = static_cast<cx<T>*>(c->V);
+        a.opV = {gptr<T>(c, 0, 1, 0), nullptr, nullptr};
+        const int64_t nynz = (int64_t)c->p.ny * c->p.nz;
+        a.S = nynz;
+        return pft::launch_spass<T>(0, c->p.nx, v, nynz, a, 1, c->stream);
+    };
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return -1;
+    }
+    double ms = -1;
+    bool ok = launch() == hipSuccess && launch() == hipSuccess;  // warm-up
+    if (ok) ok = hipEventRecord(e0, c->stream) == hipSuccess;
+    for (int i = 0; ok && i < reps; ++i) ok = launch() == hipSuccess;
+    if (ok) ok = hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float t = 0.f;
+    if (ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms;
 }
 
 }  // namespace
@@ -1214,9 +1905,16 @@ pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
     if (!pft::axis_supported(p.nx) || !pft::axis_supported(p.ny) || !pft::axis_supported(p.nz))
         return PFT_E_UNSUPPORTED;
 
+    if (!g_tune_env_checked) {
+        g_tune_env_checked = true;
+        if (const char* path = std::getenv("PFT_TUNE_CACHE")) (void)pft_tune_load(path);
+    }
     pft_ctx* c = new (std::nothrow) pft_ctx();
     if (!c) return PFT_E_NOMEM;
     c->p = p;
+    c->var[0] = tuned_variant(p.precision, p.nx, 1);
+    c->var[1] = tuned_variant(p.precision, p.ny, 1);
+    c->var[2] = tuned_variant(p.precision, p.nz, 0);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->M = (int64_t)p.nx * p.ny * p.nz;
     c->maxN = std::max(p.nx, std::max(p.ny, p.nz));
@@ -1468,6 +2166,220 @@ pft_status pft_copy_probe(const void* src, void* dst, int64_t bytes, void* strea
     hipLaunchKernelGGL(k_copy_probe, dim3(grid_for(n, 256, 4096)), dim3(256), 0, static_cast<hipStream_t>(stream),
                        static_cast<const double2*>(src), static_cast<double2*>(dst), n);
     return hipGetLastError() == hipSuccess ? PFT_OK : PFT_E_DEVICE;
+}
+
+pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_stream, pft_batch** out)
+{
+    if (!out) return PFT_E_INVALID;
+    *out = nullptr;
+    if (!params || n < 1) return PFT_E_INVALID;
+    for (int r = 1; r < n; ++r)
+        if (params[r].precision != params[0].precision || params[r].scheme != params[0].scheme) return PFT_E_INVALID;
+    pft_batch* b = new (std::nothrow) pft_batch();
+    if (!b) return PFT_E_NOMEM;
+    b->n = n;
+    b->precision = params[0].precision;
+    b->scheme = params[0].scheme;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    pft_status s = PFT_OK;
+    for (int r = 0; r < n && s == PFT_OK; ++r) {
+        pft_ctx* c = nullptr;
+        s = pft_create(&params[r], hip_stream, &c);
+        if (s == PFT_OK) b->ctx.push_back(c);
+    }
+    // group by grid shape, in order of first appearance
+    for (int r = 0; r < n && s == PFT_OK; ++r) {
+        const pft_params& p = params[r];
+        BatchGroup* g = nullptr;
+        for (BatchGroup& x : b->groups)
+            if (x.nx == p.nx && x.ny == p.ny && x.nz == p.nz) g = &x;
+        if (!g) {
+            b->groups.emplace_back();
+            g = &b->groups.back();
+            g->nx = p.nx;
+            g->ny = p.ny;
+            g->nz = p.nz;
+            g->npass = p.scheme == PFT_RQM4 ? 3 : 2;
+            const int ax3[3] = {1, 0, 1};
+            for (int k = 0; k < 3; ++k) g->sp_axis[k] = ax3[k];
+        }
+        g->reps.push_back(r);
+        for (int a = 0; a < 3; ++a) g->var[a] = b->ctx[g->reps[0]]->var[a];
+        g->maxK = std::max(g->maxK, b->ctx[r]->K);
+        g->maxM = std::max<int64_t>(g->maxM, b->ctx[r]->M);
+    }
+    if (s == PFT_OK) {
+        for (BatchGroup& g : b->groups) {
+            if (hipStreamCreateWithFlags(&g.s, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) {
+                s = PFT_E_DEVICE;
+                break;
+            }
+        }
+    }
+    if (s == PFT_OK && (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&b->in, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&b->out, hipEventDisableTiming) != hipSuccess ||
+                        hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+                        hipMalloc((void**)&b->counters, 2 * sizeof(uint64_t)) != hipSuccess ||
+                        hipMalloc((void**)&b->logj, (size_t)n * sizeof(LogJob)) != hipSuccess))
+        s = PFT_E_NOMEM;
+    if (s == PFT_OK) s = b->precision == PFT_C128 ? batch_setup_t<double>(b) : batch_setup_t<float>(b);
+    if (s != PFT_OK) {
+        (void)hipGetLastError();
+        batch_free(b);
+        delete b;
+        return s;
+    }
+    *out = b;
+    return PFT_OK;
+}
+
+void pft_batch_destroy(pft_batch* b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    if (b->own) (void)hipStreamSynchronize(b->own);
+    for (BatchGroup& g : b->groups) (void)hipStreamSynchronize(g.s);
+    batch_free(b);
+    delete b;
+}
+
+const char* pft_batch_last_error(const pft_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+static bool batch_ptrs_ok(const pft_batch* b, const double* const* p, bool optional)
+{
+    if (!p) return optional;
+    for (int r = 0; r < b->n; ++r)
+        if (!aligned16(p[r])) return false;
+    return true;
+}
+
+pft_status pft_batch_evaluate(pft_batch* b, const double* const* w_plus, const double* const* w_minus,
+                              double* const* phi_a, double* const* phi_b, double* Q, double* H)
+{
+    if (!b) return PFT_E_INVALID;
+    if (!batch_ptrs_ok(b, w_plus, false) || !batch_ptrs_ok(b, w_minus, false) ||
+        !batch_ptrs_ok(b, phi_a, false) || !batch_ptrs_ok(b, phi_b, false) || !aligned16(Q) || !aligned16(H))
+        return b->fail(PFT_E_INVALID, "pft_batch_evaluate: every pointer must be non-null and 16-byte aligned");
+    return b->precision == PFT_C128 ? batch_evaluate_t<double>(b, w_plus, w_minus, phi_a, phi_b, Q, H)
+                                    : batch_evaluate_t<float>(b, w_plus, w_minus, phi_a, phi_b, Q, H);
+}
+
+pft_status pft_batch_cl_steps(pft_batch* b, double* const* w_plus, double* const* w_minus, const pft_step* step,
+                              int32_t nsteps, double* QH_log, int64_t log_rows)
+{
+    if (!b) return PFT_E_INVALID;
+    if (!step || nsteps < 0 || !batch_ptrs_ok(b, const_cast<const double* const*>(w_plus), false) ||
+        !batch_ptrs_ok(b, const_cast<const double* const*>(w_minus), false) || (QH_log && !aligned16(QH_log)) ||
+        log_rows < 0)
+        return b->fail(PFT_E_INVALID, "pft_batch_cl_steps: bad arguments");
+    if (!(step->dt >= 0) || !(step->lambda_plus >= 0) || !(step->lambda_minus >= 0))
+        return b->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
+    const double* const* wp = const_cast<const double* const*>(w_plus);
+    const double* const* wm = const_cast<const double* const*>(w_minus);
+    return b->precision == PFT_C128 ? batch_steps_t<double>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0)
+                                    : batch_steps_t<float>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0);
+}
+
+pft_status pft_batch_sync(pft_batch* b)
+{
+    if (!b) return PFT_E_INVALID;
+    PFT_BHIP(b, hipStreamSynchronize(b->stream));
+    return PFT_OK;
+}
+
+pft_status pft_autotune(int32_t precision, const int32_t* sizes, int32_t nsizes, void* hip_stream, int32_t* choices,
+                        double* timings)
+{
+    if ((precision != PFT_C128 && precision != PFT_C64) || !sizes || nsizes < 1) return PFT_E_INVALID;
+    for (int i = 0; i < nsizes; ++i)
+        if (!pft::axis_supported(sizes[i])) return PFT_E_UNSUPPORTED;
+    for (int i = 0; i < nsizes; ++i) {
+        const int N = sizes[i];
+        const int A = tune_side(N);
+        for (int kind = 0; kind < 2; ++kind) {
+            pft_params p{};
+            p.nx = kind == 0 ? A : N;
+            p.ny = A;
+            p.nz = kind == 0 ? N : A;
+            p.lx = p.ly = p.lz = 0.1 * A;
+            if (kind == 0) p.lz = 0.1 * N; else p.lx = 0.1 * N;
+            p.ns = 2;
+            p.f = 0.5;
+            p.chiN = 10;
+            p.C = 1;
+            p.precision = precision;
+            p.scheme = PFT_SPLIT2;
+            pft_ctx* c = nullptr;
+            pft_status st = pft_create(&p, hip_stream, &c);
+            if (st) return st;
+            // the timed input: zeros are fine for timing (no data-dependent work)
+            hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(c->M * c->elem / 16, 256)), dim3(256), 0, c->stream,
+                               static_cast<double2*>(c->work), (int64_t)(c->M * c->elem / 16));
+            int best = 0;
+            double best_ms = -1;
+            for (int v = 0; v < 3; ++v) {
+                int n1, n2, w;
+                double ms = -1;
+                if (pft::axis_variant(N, v, &n1, &n2, &w))
+                    ms = precision == PFT_C128 ? time_variant<double>(c, kind, v, 10) : time_variant<float>(c, kind, v, 10);
+                if (timings) timings[(i * 2 + kind) * 3 + v] = ms;
+                if (ms > 0 && (best_ms < 0 || ms < best_ms)) {
+                    best_ms = ms;
+                    best = v;
+                }
+            }
+            pft_destroy(c);
+            if (best_ms < 0) return PFT_E_DEVICE;
+            g_tune[precision][N][kind] = best;
+            if (choices) choices[i * 2 + kind] = best;
+        }
+    }
+    return PFT_OK;
+}
+
+pft_status pft_tune_save(const char* path)
+{
+    if (!path) return PFT_E_INVALID;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return PFT_E_INVALID;
+    const std::string arch = device_arch();
+    for (int prec = 0; prec < 2; ++prec)
+        for (int n = 0; n <= 256; ++n)
+            for (int kind = 0; kind < 2; ++kind)
+                if (pft::axis_supported(n))
+                    std::fprintf(f, "%s %d %d %d %d\n", arch.c_str(), prec, n, kind, g_tune[prec][n][kind]);
+    std::fclose(f);
+    return PFT_OK;
+}
+
+pft_status pft_tune_load(const char* path)
+{
+    if (!path) return PFT_E_INVALID;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return PFT_E_INVALID;
+    const std::string arch = device_arch();
+    char a[64];
+    int prec, n, kind, v;
+    while (std::fscanf(f, "%63s %d %d %d %d", a, &prec, &n, &kind, &v) == 5) {
+        int n1, n2, w;
+        if (arch == a && (prec == 0 || prec == 1) && (kind == 0 || kind == 1) && n >= 0 && n <= 256 &&
+            pft::axis_variant(n, v, &n1, &n2, &w))
+            g_tune[prec][n][kind] = v;
+    }
+    std::fclose(f);
+    return PFT_OK;
+}
+
+pft_status pft_set_variant(pft_ctx* c, int32_t axis, int32_t variant)
+{
+    if (!c || axis < 0 || axis > 2) return PFT_E_INVALID;
+    const int n = axis == 0 ? c->p.nx : axis == 1 ? c->p.ny : c->p.nz;
+    int n1, n2, w;
+    if (!pft::axis_variant(n, variant, &n1, &n2, &w)) return c->fail(PFT_E_UNSUPPORTED, "no variant %d for %d", variant, n);
+    c->var[axis] = variant;
+    return PFT_OK;
 }
 
 pft_status pft_noise_words(uint64_t seed, uint64_t rep, uint64_t step, int32_t field, int64_t M, uint64_t* out,

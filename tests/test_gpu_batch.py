@@ -1,0 +1,89 @@
+"""Batched replicas: one launch per pass over replicas of uneven grid, contour
+step count, f and chi N, with the field step captured in a HIP graph.  Checked
+against independent single contexts (same kernels, one replica at a time), the
+oracle, and the single-context Langevin step with the same noise stream."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1204_5434_amd import binding as B
+from paper_1204_5434_amd import inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def replica_set(count, seed, prec):
+    reps = inputs.batch_replicas(count, seed)
+    params = [B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, B.PFT_RQM4) for w in reps]
+    fields = [inputs.fields(w) for w in reps]
+    return reps, params, fields
+
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_batch_evaluate_matches_single_and_oracle(orc, prec):
+    reps, params, fields = replica_set(10, 77, prec)
+    n = len(reps)
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+    pa = [torch.empty(w.n, dtype=torch.complex128, device=DEV) for w in reps]
+    pb = [torch.empty_like(t) for t in pa]
+    Q = torch.empty(n, dtype=torch.complex128, device=DEV)
+    H = torch.empty_like(Q)
+    bat.pft_batch_evaluate(wp, wm, pa, pb, Q, H)
+    bat.pft_batch_sync()
+    for r, w in enumerate(reps):
+        print("replica", r, w.n, w.ns, round(w.f, 3), flush=True)
+        ctx = B.Context(params[r])
+        out = ctx.evaluate(wp[r], wm[r])
+        assert np.abs(host(pa[r]) - host(out["phiA"])).max() <= 1e-13
+        assert abs(host(Q)[r] - host(out["Q"])[0]) <= 1e-13 * abs(host(out["Q"])[0])
+        ctx.close()
+        if r < 4:  # the oracle on a subset (it is slow at 48^3)
+            ref = orc.evaluate(orc.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, 0, False), *fields[r])
+            tol = 1e-10 if prec == B.PFT_C128 else 2e-5
+            assert np.abs(host(pa[r]) - ref["phiA"]).max() <= tol * np.abs(ref["phiA"]).max()
+            assert abs(host(Q)[r] - ref["Q"]) <= tol * abs(ref["Q"])
+            V = np.prod(w.L)
+            assert abs(host(H)[r] - ref["H"]) <= tol * (abs(ref["H"]) + w.C * V)
+
+
+def test_batch_graph_steps_match_single_steps():
+    reps, params, fields = replica_set(6, 78, B.PFT_C128)
+    n = len(reps)
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+    log = torch.zeros((5, n, 2), dtype=torch.complex128, device=DEV)
+    st = B.pft_step(0.01, 1.0, 1.0, 1208, 100, 7, 1)
+    bat.pft_batch_cl_steps(wp, wm, st, 2, log)   # captures the graph, replays twice
+    st2 = B.pft_step(0.01, 1.0, 1.0, 1208, 100, 9, 1)
+    bat.pft_batch_cl_steps(wp, wm, st2, 2, None)  # re-capture (no log), steps 9 and 10
+    bat.pft_batch_sync()
+    for r, w in enumerate(reps):
+        ctx = B.Context(params[r])
+        a, b = dev(fields[r][0]), dev(fields[r][1])
+        Qs, Hs = [], []
+        Qt = torch.empty(1, dtype=torch.complex128, device=DEV)
+        Ht = torch.empty_like(Qt)
+        for k, stepno in enumerate((7, 8, 9, 10)):
+            ctx.pft_cl_step(a, b, B.pft_step(0.01, 1.0, 1.0, 1208, 100 + r, stepno, 1), None, None, Qt, Ht)
+            Qs.append(complex(host(Qt)[0]))
+            Hs.append(complex(host(Ht)[0]))
+        assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        lg = host(log)
+        for k in range(2):
+            assert abs(lg[k, r, 0] - Qs[k]) <= 1e-12 * abs(Qs[k])
+            assert abs(lg[k, r, 1] - Hs[k]) <= 1e-12 * (abs(Hs[k]) + w.C * np.prod(w.L))
+        assert np.all(lg[2:] == 0)
+        ctx.close()

@@ -110,6 +110,36 @@ def test_diffusion_every_axis_length(orc, N):
         assert e32 < 2e-6, (n, e32)
 
 
+@pytest.mark.parametrize("N", [n for n, v in B.VARIANTS.items() if len(v) > 1])
+def test_diffusion_every_kernel_variant(orc, N):
+    """Every tile-width / radix-split variant the tuner may pick gives the oracle's result."""
+    for var in B.VARIANTS[N][1:]:
+        for axis, n in ((0, (N, 8, 12)), (1, (8, N, 12)), (2, (12, 8, N))):
+            say("variant", N, var, "axis", axis)
+            L = (0.3 * n[0], 0.25 * n[1], 0.2 * n[2])
+            u = np.random.default_rng(var).standard_normal(n) + 1j * np.random.default_rng(9).standard_normal(n)
+            ref = orc.diffuse(oparams(orc, n, L, 4, 0.5, 10.0, 1.0, 0), 0.01, u)
+            for prec, tol in ((B.PFT_C128, 1e-13), (B.PFT_C64, 2e-6)):
+                ctx = B.Context(gparams(n, L, 4, 0.5, 10.0, 1.0, 0, prec))
+                ctx.pft_set_variant(axis, var)
+                t = dev(u)
+                ctx.pft_diffuse(t, 0.01)
+                assert np.abs(host(t) - ref).max() <= tol * np.abs(ref).max(), (N, var, axis, prec)
+                ctx.close()
+
+
+def test_autotune_roundtrip(tmp_path):
+    choices, times = B.pft_autotune(B.PFT_C64, [24, 32, 48])
+    for n, (zv, sv) in choices.items():
+        assert zv in B.VARIANTS[n] and sv in B.VARIANTS[n]
+        assert min(t for t in times[n][0] if t > 0) == times[n][0][zv]
+    path = str(tmp_path / "tune.txt")
+    B.pft_tune_save(path)
+    B.pft_tune_load(path)
+    text = open(path).read()
+    assert "gfx950" in text
+
+
 @pytest.mark.parametrize("prec,tol", [(B.PFT_C128, 1e-14), (B.PFT_C64, 1e-6)])
 def test_single_mode(orc, prec, tol):
     n, L = (32, 24, 40), (3.0, 2.0, 5.0)
