@@ -38,19 +38,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_for(kernel: str, precision: str):
-    """HBM traffic per launch from the committed PMC summary, if it was taken
-    on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def traffic_for(kind: str, precision: str):
+    """HBM bytes per launch of a kernel kind from the committed counter summary
+    (profiles/lam128_hbm_traffic.txt), if it was taken on the current kernel
+    sources; else None."""
+    path = os.path.join(ROOT, "profiles", "lam128_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     try:
         from paper_1204_5434_amd import build
-        rec = json.load(open(path))
-        if rec.get("source_hash") != build.source_hash():
+        lines = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+        rec = {ln[0]: ln[1:] for ln in lines}
+        if rec.get("source_hash", [None])[0] != build.source_hash():
             return None
-        entry = rec.get("kernels", {}).get(f"{kernel}:{precision}")
-        return None if entry is None else float(entry["bytes_per_launch"])
+        entry = rec.get(f"{kind}:{precision}")
+        return None if entry is None else float(entry[0])
     except Exception:
         return None
 
@@ -67,23 +69,33 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
         ctx.pft_propagate(wp, wm)
         ctx.pft_densities(phiA, phiB, Q)
 
+    def timed(n):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(n):
+            evaluate()
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1) / n
+
     for _ in range(warmup):
         evaluate()
     torch.cuda.synchronize()
-    # timed region: exactly `steps` evaluations between two events
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(steps):
-        evaluate()
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
-    # same evaluations again with HIP events around every kernel launch
+    # timed region: exactly `steps` evaluations between two events, both sweeps
+    # running concurrently on two streams (the library's default)
+    ms = timed(steps)
+    # the same with both sweeps on one stream, for comparison
+    ctx.pft_set_concurrent_sweeps(False)
+    evaluate()
+    ms_single = timed(steps)
+    # per-kernel HIP-event timing on one stream (kernels isolated, so each
+    # launch's duration is its own)
     ctx.pft_profile_begin()
     for _ in range(steps):
         evaluate()
     prof = ctx.pft_profile_end()
+    ctx.pft_set_concurrent_sweeps(True)
     flags = ctx.pft_status_flags()
     if flags:
         raise RuntimeError(f"device status flags {flags:#x}")
@@ -105,7 +117,10 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     breakdown = {k: {"ms_per_step": round(v[0] / steps, 4), "launches_per_step": v[1] / steps,
                      "GB_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
                  for k, v in prof.items() if v[1] > 0}
-    return {"value": rate, "ms_per_step": ms, "roofline": roof, "kernels": breakdown, "Q": [Qv.real, Qv.imag]}
+    bytes_eval = sum(v[2] for v in prof.values()) / steps
+    roof["aggregate_GB_s"] = round(bytes_eval / (ms * 1e-3) / 1e9, 1)
+    return {"value": rate, "ms_per_step": ms, "ms_per_step_one_stream": ms_single, "roofline": roof,
+            "kernels": breakdown, "Q": [Qv.real, Qv.imag]}
 
 
 def batched_gain(binding, inputs, count: int, steps: int):
@@ -267,6 +282,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": main_["ms_per_step"],
+        "ms_per_step_one_stream": main_["ms_per_step_one_stream"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -284,6 +300,7 @@ def main():
         line["batched"] = batched
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
+                        "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],
                         "dtype": "f32 propagators, f64 sums", "roofline": res["f32"]["roofline"],
                         "kernels": res["f32"]["kernels"]}
     print(json.dumps(line))

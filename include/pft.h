@@ -92,6 +92,13 @@ typedef struct {
  * On failure *out is NULL and nothing stays allocated. */
 pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out);
 
+/* The q and q-dagger sweeps are independent; by default the q-dagger sweep of
+ * pft_propagate runs on a second (default-priority) stream with its own work
+ * arrays, forked from and joined back to the context stream, so the memory
+ * phases of one overlap the on-chip transform phases of the other.  on = 0
+ * runs both on the context stream.  Errors: PFT_E_INVALID. */
+pft_status pft_set_concurrent_sweeps(pft_ctx* ctx, int32_t on);
+
 /* Release everything the context owns (synchronises its stream). NULL is a no-op. */
 void pft_destroy(pft_ctx* ctx);
 

@@ -31,7 +31,7 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_status_flags", "pft_noise_words", "pft_noise_normals", "pft_profile_begin",
            "pft_profile_end", "pft_copy_probe", "pft_adjoint", "pft_batch_create", "pft_batch_destroy",
            "pft_batch_last_error", "pft_batch_evaluate", "pft_batch_cl_steps", "pft_batch_sync",
-           "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant")
+           "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant", "pft_set_concurrent_sweeps")
 
 # Kernel variants per axis length (variant 0 always exists).
 VARIANTS = {8: (0,), 12: (0,), 16: (0, 1, 2), 20: (0,), 24: (0, 1), 32: (0, 1, 2), 40: (0, 1), 48: (0, 1),
@@ -105,6 +105,7 @@ def load() -> ctypes.CDLL:
             "pft_tune_save": (i32, [ctypes.c_char_p]),
             "pft_tune_load": (i32, [ctypes.c_char_p]),
             "pft_set_variant": (i32, [vp, i32, i32]),
+            "pft_set_concurrent_sweeps": (i32, [vp, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -251,6 +252,9 @@ class Context:
                                        _field(dH_dwplus, self.shape, "dH_dwplus"),
                                        _field(dH_dwminus, self.shape, "dH_dwminus"),
                                        _opt(dH_dL, (3,), "dH_dL"), _opt(H, (1,), "H")))
+
+    def pft_set_concurrent_sweeps(self, on: bool):
+        self._check(load().pft_set_concurrent_sweeps(self._h, int(bool(on))))
 
     def pft_set_variant(self, axis: int, variant: int):
         self._check(load().pft_set_variant(self._h, axis, variant))

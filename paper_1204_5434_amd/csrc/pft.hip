@@ -779,6 +779,11 @@ struct pft_ctx {
     void* qds = nullptr;
     void* U = nullptr;
     void* V = nullptr;
+    void* U2 = nullptr;    // work pair of the conjugate sweep when it runs on s2
+    void* V2 = nullptr;
+    hipStream_t s2 = nullptr;
+    bool dual_off = false;        // run both sweeps on the context stream
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     void* E = nullptr;     // 4 * M field operator tables
     void* work = nullptr;  // 2 * M scratch in working precision
     void* gtab = nullptr;  // diffusion factors: [hid 3][half/full 2][axis 3][maxN]
@@ -832,7 +837,9 @@ struct ProfScope {
     pft_ctx* c;
     size_t i = 0;
     bool on;
-    ProfScope(pft_ctx* ctx, int kind, double bytes) : c(ctx), on(ctx->prof)
+    hipStream_t st;
+    ProfScope(pft_ctx* ctx, int kind, double bytes, hipStream_t s = nullptr)
+        : c(ctx), on(ctx->prof), st(s ? s : ctx->stream)
     {
         if (!on) return;
         i = c->ev_used;
@@ -851,11 +858,11 @@ struct ProfScope {
         c->ev_kind[i] = kind;
         c->ev_bytes[i] = bytes;
         c->ev_used = i + 1;
-        (void)hipEventRecord(c->ev[2 * i], c->stream);
+        (void)hipEventRecord(c->ev[2 * i], st);
     }
     ~ProfScope()
     {
-        if (on) (void)hipEventRecord(c->ev[2 * i + 1], c->stream);
+        if (on) (void)hipEventRecord(c->ev[2 * i + 1], st);
     }
 };
 
@@ -882,6 +889,7 @@ cx<T>* slice(void* store, const pft_ctx* c, int node)
 struct Work {
     void* U = nullptr;
     void* V = nullptr;
+    hipStream_t stream = nullptr;  // NULL: the context's stream
 };
 
 // Z pass completing step `prev` (-1: none) and starting step `next` (-1: none).
@@ -917,8 +925,9 @@ pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout, 
     if (qout) bytes += E;
     if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
     if (hcap) bytes += E;
-    ProfScope ps(c, PFT_K_ZPASS, bytes);
-    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], a, c->stream));
+    hipStream_t st = w.stream ? w.stream : c->stream;
+    ProfScope ps(c, PFT_K_ZPASS, bytes, st);
+    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], a, st));
     return PFT_OK;
 }
 
@@ -937,16 +946,17 @@ pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV, const
     if (opV.g1 && opV.acap) bytes += E;
     if (opU.g1 && opU.e) bytes += E;
     if (opV.g1 && opV.e && !(opU.g1 && opU.e == opV.e)) bytes += E;
-    ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes);
+    hipStream_t st = w.stream ? w.stream : c->stream;
+    ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes, st);
     const int64_t nynz = (int64_t)c->p.ny * c->p.nz;
     if (axis == 0) {
         a.S = nynz;
         a.slab_stride = 0;
-        PFT_HIP(c, pft::launch_spass<T>(0, c->p.nx, c->var[0], nynz, a, 1, c->stream));
+        PFT_HIP(c, pft::launch_spass<T>(0, c->p.nx, c->var[0], nynz, a, 1, st));
     } else {
         a.S = c->p.nz;
         a.slab_stride = nynz;
-        PFT_HIP(c, pft::launch_spass<T>(1, c->p.ny, c->var[1], c->p.nz, a, c->p.nx, c->stream));
+        PFT_HIP(c, pft::launch_spass<T>(1, c->p.ny, c->var[1], c->p.nz, a, c->p.nx, st));
     }
     return PFT_OK;
 }
@@ -977,16 +987,16 @@ pft_status step_body(pft_ctx* c, int j, const Work& w = Work(), cx<T>* capA = nu
 // One sweep over the K steps, forward (q) or mirrored (q-dagger), storing
 // every node into `store`.
 template <typename T>
-pft_status sweep(pft_ctx* c, bool backward, void* store)
+pft_status sweep(pft_ctx* c, bool backward, void* store, const Work& w = Work())
 {
     auto stepj = [&](int i) { return backward ? c->K - 1 - i : i; };
-    pft_status s = zpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0));
+    pft_status s = zpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0), w);
     if (s) return s;
     for (int i = 0; i < c->K; ++i) {
         const int j = stepj(i);
-        s = step_body<T>(c, j);
+        s = step_body<T>(c, j, w);
         if (s) return s;
-        s = zpass<T>(c, j, i + 1 < c->K ? stepj(i + 1) : -1, nullptr, slice<T>(store, c, i + 1));
+        s = zpass<T>(c, j, i + 1 < c->K ? stepj(i + 1) : -1, nullptr, slice<T>(store, c, i + 1), w);
         if (s) return s;
     }
     return PFT_OK;
@@ -1017,10 +1027,24 @@ pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
 {
     pft_status s = field_tables_t<T>(c, wp, wm);
     if (s) return s;
-    s = sweep<T>(c, false, c->qs);
-    if (s) return s;
-    s = sweep<T>(c, true, c->qds);
-    if (s) return s;
+    if (c->s2 && !c->dual_off) {
+        // the two sweeps are independent: the conjugate one runs on a second
+        // stream with its own work pair, so one sweep's memory phases overlap
+        // the other's on-chip transform phases
+        PFT_HIP(c, hipEventRecord(c->ev_fork, c->stream));
+        PFT_HIP(c, hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+        s = sweep<T>(c, true, c->qds, Work{c->U2, c->V2, c->s2});
+        if (s) return s;
+        PFT_HIP(c, hipEventRecord(c->ev_join, c->s2));
+        s = sweep<T>(c, false, c->qs);
+        if (s) return s;
+        PFT_HIP(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+    } else {
+        s = sweep<T>(c, false, c->qs);
+        if (s) return s;
+        s = sweep<T>(c, true, c->qds);
+        if (s) return s;
+    }
     // Q = (1/M) sum_x q_K(x)
     ProfScope ps(c, PFT_K_REDUCE, (double)c->elem * (double)c->M);
     hipLaunchKernelGGL((k_sum_partials<T>), dim3(c->nparts), dim3(kRedThreads), 0, c->stream,
@@ -1430,8 +1454,12 @@ void free_all(pft_ctx* c)
 {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
-    void* bufs[] = {c->qs,  c->qds,      c->U,        c->V,    c->E,     c->work,  c->gtab,
-                    c->tau, c->phi,      c->partials, c->scal, c->flags, c->adj,   c->adjG,
+    if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    c->s2 = nullptr;
+    void* bufs[] = {c->qs,  c->qds,  c->U,        c->V,    c->U2,    c->V2,  c->E,   c->work,
+                    c->gtab, c->tau, c->phi,      c->partials, c->scal, c->flags, c->adj, c->adjG,
                     c->adjAcc};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -1892,7 +1920,28 @@ int32_t pft_contour_plan(int32_t ns, double f, double* h, int32_t* blk, int32_t*
     return K;
 }
 
+static pft_status create_ctx(const pft_params* params, void* hip_stream, bool dual, pft_ctx** out);
+
 pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
+{
+    return create_ctx(params, hip_stream, true, out);
+}
+
+pft_status pft_set_concurrent_sweeps(pft_ctx* c, int32_t on)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!on) {
+        (void)hipStreamSynchronize(c->stream);
+        if (c->s2) (void)hipStreamSynchronize(c->s2);
+        c->dual_off = true;
+    } else {
+        if (!c->s2) return c->fail(PFT_E_UNSUPPORTED, "this context was created without a second stream");
+        c->dual_off = false;
+    }
+    return PFT_OK;
+}
+
+static pft_status create_ctx(const pft_params* params, void* hip_stream, bool dual, pft_ctx** out)
 {
     if (!out) return PFT_E_INVALID;
     *out = nullptr;
@@ -1949,7 +1998,8 @@ pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
     auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess; };
     const size_t store = (size_t)(c->K + 1) * c->M * c->elem;
     bool ok = alloc(&c->qs, store) && alloc(&c->qds, store) && alloc(&c->U, c->M * c->elem) &&
-              alloc(&c->V, c->M * c->elem) && alloc(&c->E, 4 * c->M * c->elem) && alloc(&c->work, 2 * c->M * c->elem) &&
+              alloc(&c->V, c->M * c->elem) && (!dual || (alloc(&c->U2, c->M * c->elem) && alloc(&c->V2, c->M * c->elem))) &&
+              alloc(&c->E, 4 * c->M * c->elem) && alloc(&c->work, 2 * c->M * c->elem) &&
               alloc(&c->gtab, (size_t)5 * 2 * 3 * c->maxN * (c->elem / 2)) &&
               alloc((void**)&c->tau, tau.size() * sizeof(double)) && alloc((void**)&c->phi, 2 * c->M * sizeof(double2)) &&
               alloc((void**)&c->partials, (size_t)std::max(c->nparts, 64 * (c->K + 1)) * sizeof(double2)) &&
@@ -1961,6 +2011,10 @@ pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
         return PFT_E_NOMEM;
     }
     pft_status s = PFT_OK;
+    if (dual && (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
+                 hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                 hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess))
+        s = PFT_E_DEVICE;
     if (hipMemcpy(c->tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->flags, 0, sizeof(uint32_t)) != hipSuccess || hipMemset(c->scal, 0, (8 + c->K + 1) * sizeof(double2)) != hipSuccess)
         s = PFT_E_DEVICE;
@@ -1982,6 +2036,7 @@ void pft_destroy(pft_ctx* c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->s2) (void)hipStreamSynchronize(c->s2);
     free_all(c);
     delete c;
 }
@@ -2184,7 +2239,7 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     pft_status s = PFT_OK;
     for (int r = 0; r < n && s == PFT_OK; ++r) {
         pft_ctx* c = nullptr;
-        s = pft_create(&params[r], hip_stream, &c);
+        s = create_ctx(&params[r], hip_stream, false, &c);
         if (s == PFT_OK) b->ctx.push_back(c);
     }
     // group by grid shape, in order of first appearance
