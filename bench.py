@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "propagator grid-pts×steps/s + %HBM peak, FP32 vs FP64 plain at 128³ Ns=100"
 HBM_PEAK_GBS = 8000.0
 PROFILE_KIND = {"zpass": "k_zpass", "ypass": "k_spass<..,1>", "xpass": "k_spass<..,0>",
-                "density": "k_density", "tables": "k_field_tables", "reduce": "reductions"}
+                "yzpass": "k_yzpass", "density": "k_density", "tables": "k_field_tables",
+                "reduce": "reductions"}
 
 
 def log(*a):
@@ -79,12 +80,21 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / n
 
+    fused = ctx.pft_fused_planes()
     for _ in range(warmup):
         evaluate()
     torch.cuda.synchronize()
     # timed region: exactly `steps` evaluations between two events, both sweeps
     # running concurrently on two streams (the library's default)
     ms = timed(steps)
+    ms_axis = None
+    if fused:
+        # the same with the axis schedule (four passes per step), for comparison
+        ctx.pft_set_fused_planes(False)
+        evaluate()
+        ms_axis = timed(steps)
+        ctx.pft_set_fused_planes(True)
+        evaluate()
     # the same with both sweeps on one stream, for comparison
     ctx.pft_set_concurrent_sweeps(False)
     evaluate()
@@ -104,7 +114,7 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     site_steps = 2.0 * w.M * w.ns
     rate = site_steps / (ms * 1e-3)
     # dominant kernel by measured time among the memory-pass kernels
-    kinds = [k for k in ("zpass", "ypass", "xpass", "density") if prof[k][1] > 0]
+    kinds = [k for k in ("zpass", "ypass", "xpass", "yzpass", "density") if prof[k][1] > 0]
     dom = max(kinds, key=lambda k: prof[k][0])
     kms, kn, kbytes = prof[dom]
     per_launch_ms = kms / kn
@@ -119,8 +129,11 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
                  for k, v in prof.items() if v[1] > 0}
     bytes_eval = sum(v[2] for v in prof.values()) / steps
     roof["aggregate_GB_s"] = round(bytes_eval / (ms * 1e-3) / 1e9, 1)
-    return {"value": rate, "ms_per_step": ms, "ms_per_step_one_stream": ms_single, "roofline": roof,
-            "kernels": breakdown, "Q": [Qv.real, Qv.imag]}
+    out = {"value": rate, "ms_per_step": ms, "ms_per_step_one_stream": ms_single, "roofline": roof,
+           "kernels": breakdown, "Q": [Qv.real, Qv.imag], "schedule": "fused-yz" if fused else "axis"}
+    if ms_axis is not None:
+        out["ms_per_step_axis_schedule"] = ms_axis
+    return out
 
 
 def batched_gain(binding, inputs, count: int, steps: int):
@@ -237,10 +250,15 @@ def main():
         n = args.copy_probe_mib * (1 << 20) // 16
         a = torch.zeros(n, dtype=torch.complex128, device="cuda")
         b = torch.empty_like(a)
-        for _ in range(3):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        binding.pft_copy_probe(a, b)
+        ev[0].record()
+        for _ in range(2):
             binding.pft_copy_probe(a, b)
+        ev[1].record()
         torch.cuda.synchronize()
-        log(f"[bench] copy probe: 3 x {args.copy_probe_mib} MiB")
+        copy_gbs = 2 * 2 * a.numel() * 16 / (ev[0].elapsed_time(ev[1]) * 1e-3) / 1e9
+        log(f"[bench] copy probe: 3 x {args.copy_probe_mib} MiB, {copy_gbs:.0f} GB/s (read + write)")
         del a, b
     tuned = None
     if args.tune_file and os.path.exists(args.tune_file):
@@ -293,7 +311,10 @@ def main():
         "roofline": main_["roofline"],
         "cpu_baseline": cpu,
         "kernels": main_["kernels"],
+        "schedule": main_["schedule"],
     }
+    if "ms_per_step_axis_schedule" in main_:
+        line["ms_per_step_axis_schedule"] = main_["ms_per_step_axis_schedule"]
     if tuned is not None:
         line["kernel_variants"] = tuned
     if batched is not None:
@@ -302,7 +323,9 @@ def main():
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],
                         "dtype": "f32 propagators, f64 sums", "roofline": res["f32"]["roofline"],
-                        "kernels": res["f32"]["kernels"]}
+                        "kernels": res["f32"]["kernels"], "schedule": res["f32"]["schedule"]}
+        if "ms_per_step_axis_schedule" in res["f32"]:
+            line["fp32"]["ms_per_step_axis_schedule"] = res["f32"]["ms_per_step_axis_schedule"]
     print(json.dumps(line))
 
 

@@ -99,6 +99,20 @@ pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
  * runs both on the context stream.  Errors: PFT_E_INVALID. */
 pft_status pft_set_concurrent_sweeps(pft_ctx* ctx, int32_t on);
 
+/* Schedule of the sweeps (Eq. (12) either way; results agree to rounding).
+ * The axis schedule runs a step as four memory passes (z, y, x, y).  When
+ * ny == nz and one yz-plane fits in the 160 KB LDS of a compute unit (complex
+ * float: up to 128 x 128; complex double: up to 96 x 96) the y, z, y passes
+ * between two x passes fuse into one pass per x-plane, and a step moves 11
+ * instead of 17 arrays.  New contexts use the fused schedule where it exists.
+ * The schedule applies to pft_propagate, pft_cl_step and pft_apply_step; the
+ * reverse mode (pft_adjoint) and batches always use the axis schedule.
+ * on = 1 without a fused kernel for the shape: PFT_E_UNSUPPORTED (schedule
+ * unchanged).  pft_fused_planes returns 1 / 0 for the current schedule, -1
+ * for NULL. */
+pft_status pft_set_fused_planes(pft_ctx* ctx, int32_t on);
+int32_t pft_fused_planes(const pft_ctx* ctx);
+
 /* Release everything the context owns (synchronises its stream). NULL is a no-op. */
 void pft_destroy(pft_ctx* ctx);
 
@@ -273,7 +287,8 @@ typedef enum {
     PFT_K_XPASS = 3,   /* x-axis pass                                            */
     PFT_K_DENSITY = 4, /* contour-weighted q * q-dagger reduction               */
     PFT_K_REDUCE = 5,  /* spatial reductions (Q, H, per-node Q) and the update   */
-    PFT_K_COUNT = 6
+    PFT_K_YZPASS = 6,  /* fused yz-plane pass (y, z, y of two steps)             */
+    PFT_K_COUNT = 7
 } pft_kernel_kind;
 
 /* Per-kernel timing for roofline measurement.  Between pft_profile_begin and

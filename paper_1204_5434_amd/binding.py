@@ -31,13 +31,17 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_status_flags", "pft_noise_words", "pft_noise_normals", "pft_profile_begin",
            "pft_profile_end", "pft_copy_probe", "pft_adjoint", "pft_batch_create", "pft_batch_destroy",
            "pft_batch_last_error", "pft_batch_evaluate", "pft_batch_cl_steps", "pft_batch_sync",
-           "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant", "pft_set_concurrent_sweeps")
+           "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant", "pft_set_concurrent_sweeps",
+           "pft_set_fused_planes", "pft_fused_planes")
 
 # Kernel variants per axis length (variant 0 always exists).
 VARIANTS = {8: (0,), 12: (0,), 16: (0, 1, 2), 20: (0,), 24: (0, 1), 32: (0, 1, 2), 40: (0, 1), 48: (0, 1),
             64: (0, 1, 2), 80: (0,), 96: (0, 1), 128: (0, 1), 192: (0,), 256: (0, 1)}
 
-KERNEL_KINDS = ("tables", "zpass", "ypass", "xpass", "density", "reduce")
+KERNEL_KINDS = ("tables", "zpass", "ypass", "xpass", "density", "reduce", "yzpass")
+
+# Square yz-plane sides with a fused yz pass, per precision (complex double, complex float).
+FUSED_PLANES = {0: (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96), 1: (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128)}
 
 
 class PftError(RuntimeError):
@@ -106,6 +110,8 @@ def load() -> ctypes.CDLL:
             "pft_tune_load": (i32, [ctypes.c_char_p]),
             "pft_set_variant": (i32, [vp, i32, i32]),
             "pft_set_concurrent_sweeps": (i32, [vp, i32]),
+            "pft_set_fused_planes": (i32, [vp, i32]),
+            "pft_fused_planes": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -255,6 +261,12 @@ class Context:
 
     def pft_set_concurrent_sweeps(self, on: bool):
         self._check(load().pft_set_concurrent_sweeps(self._h, int(bool(on))))
+
+    def pft_set_fused_planes(self, on: bool):
+        self._check(load().pft_set_fused_planes(self._h, int(bool(on))))
+
+    def pft_fused_planes(self) -> bool:
+        return load().pft_fused_planes(self._h) == 1
 
     def pft_set_variant(self, axis: int, variant: int):
         self._check(load().pft_set_variant(self._h, axis, variant))

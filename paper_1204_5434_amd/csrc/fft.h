@@ -12,7 +12,8 @@
 //
 // Twiddles are evaluated in double precision at compile time (Taylor series on
 // an exact integer reduction of the angle) and rounded once to the working
-// precision; nothing comes from a recurrence.
+// precision; a twiddle that depends on the lane is the product of at most two
+// such table entries, and nothing comes from a recurrence.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -156,15 +157,39 @@ __device__ __forceinline__ cx<T> rot(cx<T> x)
     }
 }
 
-// x * e^{-+2 pi i a / N} with a runtime in [0, N): table lookup.
-template <int N, bool INV, typename T>
-__device__ __forceinline__ cx<T> rot_rt(cx<T> x, int a)
+// a[k1] *= W_N^{-+ t k1} for k1 = 1 .. N1-1 (forward: minus).  With k1 = 4 m + l
+// the factor is the product of the table entries W^{t l} and W^{4 t m}, so a
+// lane reads 3 + (N1 - 1) / 4 roots instead of N1 - 1.
+template <int N1, int N, bool INV, typename T>
+__device__ __forceinline__ void twiddle(cx<T> (&a)[N1], int t)
 {
-    const cx<T> w = kRoots<T, N>.w[a];
-    if constexpr (INV)
-        return {w.re * x.re + w.im * x.im, w.re * x.im - w.im * x.re};
-    else
-        return {w.re * x.re - w.im * x.im, w.re * x.im + w.im * x.re};
+    constexpr int ML = (N1 - 1) / 4;
+    cx<T> lo[4], hi[ML + 1];
+    sfor<1, (N1 < 4 ? N1 : 4)>([&](auto L) {
+        constexpr int l = decltype(L)::value;
+        lo[l] = kRoots<T, N>.w[(t * l) % N];
+    });
+    sfor<1, ML + 1>([&](auto Mi) {
+        constexpr int m = decltype(Mi)::value;
+        hi[m] = kRoots<T, N>.w[(t * 4 * m) % N];
+    });
+    sfor<1, N1>([&](auto K1) {
+        constexpr int k1 = decltype(K1)::value;
+        constexpr int l = k1 % 4, m = k1 / 4;
+        cx<T> w;
+        if constexpr (m == 0) {
+            w = lo[l];
+        } else if constexpr (l == 0) {
+            w = hi[m];
+        } else {
+            w = lo[l] * hi[m];
+        }
+        const cx<T> x = a[k1];
+        if constexpr (INV)
+            a[k1] = {w.re * x.re + w.im * x.im, w.re * x.im - w.im * x.re};
+        else
+            a[k1] = {w.re * x.re - w.im * x.im, w.re * x.im + w.im * x.re};
+    });
 }
 
 // ------------------------------------------------------ in-register DFTs --
@@ -317,10 +342,7 @@ __device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict
         static_assert(N1 % N2 == 0, "each lane must own whole stage-two transforms");
         constexpr int NB = N1 / N2;
         dft<N1, false>(a);
-        sfor<1, N1>([&](auto K1) {
-            constexpr int k1 = decltype(K1)::value;
-            a[k1] = rot_rt<N, false>(a[k1], (t * k1) % N);
-        });
+        twiddle<N1, N, false>(a, t);
         __syncthreads();
         sfor<0, N1>([&](auto K1) { sh[lay(decltype(K1)::value, t)] = a[decltype(K1)::value]; });
         __syncthreads();
@@ -345,10 +367,7 @@ __device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict
         });
         __syncthreads();
         sfor<0, N1>([&](auto K1) { a[decltype(K1)::value] = sh[lay(decltype(K1)::value, t)]; });
-        sfor<1, N1>([&](auto K1) {
-            constexpr int k1 = decltype(K1)::value;
-            a[k1] = rot_rt<N, true>(a[k1], (t * k1) % N);
-        });
+        twiddle<N1, N, true>(a, t);
         dft<N1, true>(a);
     }
 }

@@ -16,6 +16,7 @@
 
 #include "../../include/pft.h"
 #include "kernels.h"
+#include "planes.h"
 
 using pft::cx;
 
@@ -773,6 +774,7 @@ struct pft_ctx {
     double hval[3] = {0, 0, 0};       // ds, A junction sub-step, B junction sub-step
     int maxN = 0;
     int var[3] = {0, 0, 0};           // kernel variant of each axis pass (x, y, z)
+    bool fused = false;               // sweeps use the fused yz-plane pass (square yz-plane in LDS)
     size_t elem = 0;                  // bytes per propagator value
     // device buffers
     void* qs = nullptr;
@@ -961,6 +963,61 @@ pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV, const
     return PFT_OK;
 }
 
+// Fused yz-plane pass completing step `prev` (-1: none: its Y2 and Z) and
+// starting step `next` (-1: none: its Z and Y1).
+template <typename T>
+pft_status yzpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout, const Work& w = Work(),
+                  cx<T>* hcap = nullptr)
+{
+    pft::PArgs<T> a{};
+    a.nplanes = c->p.nx;
+    a.U = static_cast<cx<T>*>(w.U ? w.U : c->U);
+    a.V = static_cast<cx<T>*>(w.V ? w.V : c->V);
+    a.hcap = hcap;
+    a.qin = qin;
+    a.qout = qout;
+    a.scheme = c->p.scheme;
+    a.has_prev = prev >= 0;
+    a.has_next = next >= 0;
+    if (prev >= 0) {
+        a.Ep = etab<T>(c, c->kind[prev]);
+        a.gyh_p = gptr<T>(c, c->hid[prev], 0, 1);
+        a.gzh_p = gptr<T>(c, c->hid[prev], 0, 2);
+    }
+    if (next >= 0) {
+        a.En = etab<T>(c, c->kind[next]);
+        a.gzh_n = gptr<T>(c, c->hid[next], 0, 2);
+        a.gzf_n = gptr<T>(c, c->hid[next], 1, 2);
+        a.gyh_n = gptr<T>(c, c->hid[next], 0, 1);
+        a.gyf_n = gptr<T>(c, c->hid[next], 1, 1);
+    }
+    // algorithmic bytes, as for the z pass
+    const double E = (double)c->elem * (double)c->M;
+    const bool rqm4 = c->p.scheme == PFT_RQM4;
+    double bytes = 0;
+    if (prev >= 0) bytes += (rqm4 ? 3 : 2) * E;
+    else if (qin) bytes += E;
+    if (qout) bytes += E;
+    if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
+    if (hcap) bytes += E;
+    hipStream_t st = w.stream ? w.stream : c->stream;
+    ProfScope ps(c, PFT_K_YZPASS, bytes, st);
+    PFT_HIP(c, pft::launch_yzpass<T>(c->p.ny, a, st));
+    return PFT_OK;
+}
+
+// The x pass of step j alone (the fused schedule's other pass).
+template <typename T>
+pft_status xpass_step(pft_ctx* c, int j, const Work& w = Work(), cx<T>* capA = nullptr, cx<T>* capC = nullptr)
+{
+    const int hd = c->hid[j];
+    const cx<T>* e = etab<T>(c, c->kind[j]);
+    if (c->p.scheme == PFT_RQM4)
+        return spass<T>(c, 0, {gptr<T>(c, hd, 0, 0), e, gptr<T>(c, hd, 0, 0), capA},
+                        {gptr<T>(c, hd, 1, 0), e, nullptr, capC}, w);
+    return spass<T>(c, 0, {nullptr, nullptr, nullptr}, {gptr<T>(c, hd, 1, 0), nullptr, nullptr}, w);
+}
+
 // The Y1, X, Y2 passes of step j (Y, X for the plain split).  capA / capC,
 // if set, receive D_{h/2} E4 q (half path after its first diffusion) and
 // D_h E2 q (full path before its last multiply) from the x pass.
@@ -990,6 +1047,19 @@ template <typename T>
 pft_status sweep(pft_ctx* c, bool backward, void* store, const Work& w = Work())
 {
     auto stepj = [&](int i) { return backward ? c->K - 1 - i : i; };
+    if (c->fused) {
+        // two passes per step: X, then yz completing it and starting the next
+        pft_status s = yzpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0), w);
+        if (s) return s;
+        for (int i = 0; i < c->K; ++i) {
+            const int j = stepj(i);
+            s = xpass_step<T>(c, j, w);
+            if (s) return s;
+            s = yzpass<T>(c, j, i + 1 < c->K ? stepj(i + 1) : -1, nullptr, slice<T>(store, c, i + 1), w);
+            if (s) return s;
+        }
+        return PFT_OK;
+    }
     pft_status s = zpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0), w);
     if (s) return s;
     for (int i = 0; i < c->K; ++i) {
@@ -1115,11 +1185,20 @@ pft_status apply_step_t(pft_ctx* c, int j, const double* qin, double* qout)
     hipLaunchKernelGGL((k_to_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
                        reinterpret_cast<const double2*>(qin), w0, c->M);
     PFT_HIP(c, hipGetLastError());
-    pft_status s = zpass<T>(c, -1, j, w0, nullptr);
-    if (s) return s;
-    s = step_body<T>(c, j);
-    if (s) return s;
-    s = zpass<T>(c, j, -1, nullptr, w1);
+    pft_status s;
+    if (c->fused) {
+        s = yzpass<T>(c, -1, j, w0, nullptr);
+        if (s) return s;
+        s = xpass_step<T>(c, j);
+        if (s) return s;
+        s = yzpass<T>(c, j, -1, nullptr, w1);
+    } else {
+        s = zpass<T>(c, -1, j, w0, nullptr);
+        if (s) return s;
+        s = step_body<T>(c, j);
+        if (s) return s;
+        s = zpass<T>(c, j, -1, nullptr, w1);
+    }
     if (s) return s;
     hipLaunchKernelGGL((k_from_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream, w1,
                        reinterpret_cast<double2*>(qout), c->M);
@@ -1941,6 +2020,23 @@ pft_status pft_set_concurrent_sweeps(pft_ctx* c, int32_t on)
     return PFT_OK;
 }
 
+static bool fused_supported(const pft_params& p)
+{
+    if (p.ny != p.nz) return false;
+    return p.precision == PFT_C128 ? pft::plane_supported<double>(p.ny) : pft::plane_supported<float>(p.ny);
+}
+
+pft_status pft_set_fused_planes(pft_ctx* c, int32_t on)
+{
+    if (!c) return PFT_E_INVALID;
+    if (on && !fused_supported(c->p))
+        return c->fail(PFT_E_UNSUPPORTED, "no fused yz-plane pass for a %d x %d plane in this precision", c->p.ny, c->p.nz);
+    c->fused = on != 0;
+    return PFT_OK;
+}
+
+int32_t pft_fused_planes(const pft_ctx* c) { return c ? (c->fused ? 1 : 0) : -1; }
+
 static pft_status create_ctx(const pft_params* params, void* hip_stream, bool dual, pft_ctx** out)
 {
     if (!out) return PFT_E_INVALID;
@@ -1964,6 +2060,7 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
     c->var[0] = tuned_variant(p.precision, p.nx, 1);
     c->var[1] = tuned_variant(p.precision, p.ny, 1);
     c->var[2] = tuned_variant(p.precision, p.nz, 0);
+    c->fused = fused_supported(p);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->M = (int64_t)p.nx * p.ny * p.nz;
     c->maxN = std::max(p.nx, std::max(p.ny, p.nz));

@@ -99,13 +99,22 @@ def test_split2_gradient_is_the_force():
 def test_gradient_state_fd_and_force():
     """96^3, Ns = 128, f = 0.3 (junction), checkpoints every 11 steps: per-site
     4th-order differences of the GPU's own H at 64 sites, a directional
-    difference along the lamellar mode, and the analytic density force."""
+    difference along the lamellar mode, and the analytic density force.
+
+    The reverse mode runs the axis schedule; the differences of H are taken on
+    that schedule too (the fused schedule's H agrees to rounding, checked
+    first), so that only one rounding pattern enters the per-site noise floor."""
     w = inputs.GRAD96
     wp, wm = inputs.fields(w)
     ctx = B.Context(B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, B.PFT_C128, B.PFT_RQM4))
     gwp, gwm = dev(wp), dev(wm)
     gp, gm, dL, H0 = gpu_adjoint(ctx, gwp, gwm, kc=11)
     Hbuf = torch.empty(1, dtype=torch.complex128, device=DEV)
+    assert ctx.pft_fused_planes()
+    ctx.pft_propagate(gwp, gwm)
+    ctx.pft_hamiltonian(gwp, gwm, Hbuf)
+    assert abs(complex(host(Hbuf)[0]) - H0) <= 1e-12 * abs(H0)
+    ctx.pft_set_fused_planes(False)
 
     def H(ap, am):
         ctx.pft_propagate(ap, am)
@@ -115,7 +124,9 @@ def test_gradient_state_fd_and_force():
     assert abs(H(gwp, gwm) - H0) <= 1e-12 * abs(H0)
     rng = np.random.default_rng(7)
     sites = [tuple(s) for s in rng.integers(0, 96, size=(64, 3))]
-    eps = 1e-4
+    # the step balances H's rounding noise (~1e-14 |H|, falling as 1/eps in the
+    # difference) against the O(eps^4) truncation error (< 1e-7 up to eps = 6e-3)
+    eps = 1e-3
     worst = 0.0
     for k, site in enumerate(sites):
         which = k % 2
@@ -147,6 +158,7 @@ def test_gradient_state_fd_and_force():
             Ls = list(w.L)
             Ls[a] += e
             c2 = B.Context(B.Params(*w.n, *Ls, w.ns, w.f, w.chiN, w.C, B.PFT_C128, B.PFT_RQM4))
+            c2.pft_set_fused_planes(False)
             c2.pft_propagate(gwp, gwm)
             c2.pft_hamiltonian(gwp, gwm, Hbuf)
             v = complex(host(Hbuf)[0])

@@ -1,0 +1,125 @@
+"""GPU parity of the fused yz-plane schedule: for every square yz-plane side
+with a fused kernel, in both working precisions, the full evaluation (q and
+q-dagger sweeps, densities, Q, H) against the FP64 oracle, and against the
+axis schedule of the same context.
+
+Ly != Lz in every case, so a y/z mix-up of the diffusion factors or of the
+plane transpose fails; nx is chosen so that workgroups holding several small
+planes have idle planes (ragged tail).  Bars as in test_gpu_parity.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1204_5434_amd import binding as B
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rand_fields(shape, seed):
+    r = np.random.default_rng(seed)
+    wp = 0.3 * r.standard_normal(shape) + 0.1j * r.standard_normal(shape)
+    wm = 0.3 * r.standard_normal(shape) + 0.1j * r.standard_normal(shape)
+    return wp, wm
+
+
+def case_for(N, k):
+    """(n, L, ns, f, chiN, C, scheme) for plane side N; k varies the contour."""
+    nx = 20 if N <= 16 else (12 if N <= 64 else 8)
+    L = (0.2 * nx, 0.2 * N, 0.15 * N)
+    contour = [(25, 0.3, 0), (13, 0.62, 1), (16, 0.5, 0)][k % 3]
+    ns, f, scheme = contour
+    return (nx, N, N), L, ns, f, 15.0, 1.5, scheme
+
+
+CASES = [(prec, N) for prec in (B.PFT_C128, B.PFT_C64) for N in B.FUSED_PLANES[prec]]
+
+
+def evaluate(ctx, wp, wm):
+    out = ctx.evaluate(dev(wp), dev(wm))
+    return {k: host(v) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("prec,N", CASES, ids=[f"{'c128' if p == 0 else 'c64'}-{n}" for p, n in CASES])
+def test_fused_schedule_matches_oracle(orc, prec, N):
+    k = B.FUSED_PLANES[prec].index(N)
+    n, L, ns, f, chiN, C, scheme = case_for(N, k)
+    say("fused schedule", prec, n, ns, f, scheme)
+    wp, wm = rand_fields(n, 100 + N)
+    ref = orc.evaluate(orc.Params(*n, *L, ns, f, chiN, C, scheme, False), wp, wm)
+    ctx = B.Context(B.Params(*n, *L, ns, f, chiN, C, prec, scheme))
+    assert ctx.pft_fused_planes()  # the default where the kernel exists
+    fused = evaluate(ctx, wp, wm)
+    ctx.pft_set_fused_planes(False)
+    assert not ctx.pft_fused_planes()
+    axis = evaluate(ctx, wp, wm)
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
+    V = np.prod(L)
+    for got in (fused, axis):
+        if prec == B.PFT_C128:
+            for key in ("phiA", "phiB"):
+                assert np.abs(got[key] - ref[key]).max() <= 1e-10, key
+            assert abs(got["Q"][0] - ref["Q"]) <= 1e-11 * abs(ref["Q"])
+            assert abs(got["H"][0] - ref["H"]) <= 1e-11 * (abs(ref["H"]) + C * V)
+        else:
+            for key in ("phiA", "phiB"):
+                assert np.abs(got[key] - ref[key]).max() <= 2e-5 * np.abs(ref[key]).max(), key
+            assert abs(got["Q"][0] - ref["Q"]) <= 2e-5 * abs(ref["Q"])
+            assert abs(got["H"][0] - ref["H"]) <= 2e-5 * (abs(ref["H"]) + C * V)
+    # the two schedules apply the same operators in another order
+    tol = 1e-12 if prec == B.PFT_C128 else 1e-5
+    scale = np.abs(axis["phiA"]).max()
+    assert np.abs(fused["phiA"] - axis["phiA"]).max() <= tol * scale
+
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_fused_apply_step_and_slices(orc, prec):
+    """One step through pft_apply_step on the fused schedule, and the stored
+    slices of a sweep, against the oracle's single step."""
+    n, L = (12, 48, 48), (3.0, 6.0, 4.5)
+    ns, f = 10, 0.45
+    wp, wm = rand_fields(n, 7)
+    p_or = orc.Params(*n, *L, ns, f, 15.0, 1.0, 0, False)
+    ctx = B.Context(B.Params(*n, *L, ns, f, 15.0, 1.0, prec, 0))
+    assert ctx.pft_fused_planes()
+    ctx.evaluate(dev(wp), dev(wm))
+    wA, wB = orc.block_fields(p_or, wp, wm)
+    h, blk, _ = orc.contour(ns, f)
+    tol = 1e-12 if prec == B.PFT_C128 else 2e-5
+    qj = torch.empty(n, dtype=torch.complex128, device=DEV)
+    qj1 = torch.empty_like(qj)
+    out = torch.empty_like(qj)
+    for j in (0, 4, ctx.K - 1):
+        ctx.pft_get_slice(0, j, qj)
+        ctx.pft_get_slice(0, j + 1, qj1)
+        ref = orc.step(p_or, h[j], wA if blk[j] == 0 else wB, host(qj))
+        assert np.abs(host(qj1) - ref).max() <= tol * np.abs(ref).max(), j
+        ctx.pft_apply_step(j, qj, out)
+        assert np.abs(host(out) - ref).max() <= tol * np.abs(ref).max(), j
+    ctx.close()
+
+
+def test_fused_unsupported_shapes():
+    # non-square yz-plane, and a complex-double plane too large for LDS
+    for n, prec in (((16, 16, 32), B.PFT_C128), ((8, 128, 128), B.PFT_C128), ((8, 256, 256), B.PFT_C64)):
+        ctx = B.Context(B.Params(*n, 1.0, 1.0, 1.0, 4, 0.5, 10.0, 1.0, prec, 0))
+        assert not ctx.pft_fused_planes()
+        with pytest.raises(B.PftError) as e:
+            ctx.pft_set_fused_planes(True)
+        assert e.value.status == B.PFT_E_UNSUPPORTED
+        assert not ctx.pft_fused_planes()
+        ctx.close()
