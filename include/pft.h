@@ -256,15 +256,21 @@ pft_status pft_batch_cl_steps(pft_batch* batch, double* const* w_plus, double* c
                               const pft_step* step, int32_t nsteps, double* QH_log, int64_t log_rows);
 pft_status pft_batch_sync(pft_batch* batch);
 
+#define PFT_MAX_VARIANTS 4
+
 /* ---- autotuner ---------------------------------------------------------------
- * Every axis length has up to three kernel variants of its passes (workgroup
- * tile width, radix split N = N1 * N2; all give the same results to rounding).
- * pft_autotune times every variant of the z pass and of the strided passes for
- * each listed axis length on the current device (grids of ~4 Mi sites) and
- * makes the fastest the default for contexts and batches created afterwards.
+ * Every axis length has up to PFT_MAX_VARIANTS kernel variants of its passes
+ * (workgroup tile width, radix split N = N1 * N2, register bound for two waves
+ * per SIMD; all give the same results to rounding).  pft_autotune times every
+ * variant of the z pass and of the strided passes for each listed axis length
+ * on the current device (grids of ~4 Mi sites; the z pass completing and
+ * starting a Richardson step, the strided kind as an x pass on both arrays
+ * with its field multiply) and makes the fastest the default for
+ * contexts and batches created afterwards.
  * choices (may be NULL): 2 ints per size (z variant, strided variant);
- * timings (may be NULL): 6 doubles per size (ms per launch, z then strided,
- * variants 0..2, -1 where a variant does not exist).  Synchronous.
+ * timings (may be NULL): 2 * PFT_MAX_VARIANTS doubles per size (ms per launch,
+ * z then strided, variants 0.., -1 where a variant does not exist).
+ * Synchronous.
  * Errors: PFT_E_INVALID, PFT_E_UNSUPPORTED, PFT_E_NOMEM, PFT_E_DEVICE. */
 pft_status pft_autotune(int32_t precision, const int32_t* sizes, int32_t nsizes, void* hip_stream,
                         int32_t* choices, double* timings);

@@ -34,9 +34,10 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant", "pft_set_concurrent_sweeps",
            "pft_set_fused_planes", "pft_fused_planes")
 
-# Kernel variants per axis length (variant 0 always exists).
+# Kernel variants per axis length (variant 0 always exists), at most MAX_VARIANTS.
+MAX_VARIANTS = 4
 VARIANTS = {8: (0,), 12: (0,), 16: (0, 1, 2), 20: (0,), 24: (0, 1), 32: (0, 1, 2), 40: (0, 1), 48: (0, 1),
-            64: (0, 1, 2), 80: (0,), 96: (0, 1), 128: (0, 1), 192: (0,), 256: (0, 1)}
+            64: (0, 1, 2, 3), 80: (0,), 96: (0, 1), 128: (0, 1, 2), 192: (0,), 256: (0, 1)}
 
 KERNEL_KINDS = ("tables", "zpass", "ypass", "xpass", "density", "reduce", "yzpass")
 
@@ -379,16 +380,17 @@ class Batch:
 
 def pft_autotune(precision: int, sizes):
     """Time every kernel variant for each axis length; returns
-    ({N: (z variant, strided variant)}, {N: [[z ms x3], [strided ms x3]]})."""
+    ({N: (z variant, strided variant)}, {N: [[z ms per variant], [strided ms per variant]]})."""
     import numpy as np
+    nv = MAX_VARIANTS
     sz = np.ascontiguousarray(sizes, dtype=np.int32)
     ch = np.zeros(2 * len(sz), dtype=np.int32)
-    tm = np.zeros(6 * len(sz))
+    tm = np.zeros(2 * nv * len(sz))
     st = load().pft_autotune(precision, sz.ctypes.data, len(sz), _stream(), ch.ctypes.data, tm.ctypes.data)
     if st != PFT_OK:
         raise PftError(st, "pft_autotune failed")
     return ({int(n): (int(ch[2 * i]), int(ch[2 * i + 1])) for i, n in enumerate(sz)},
-            {int(n): tm[6 * i:6 * i + 6].reshape(2, 3).tolist() for i, n in enumerate(sz)})
+            {int(n): tm[2 * nv * i:2 * nv * (i + 1)].reshape(2, nv).tolist() for i, n in enumerate(sz)})
 
 
 def pft_tune_save(path: str):

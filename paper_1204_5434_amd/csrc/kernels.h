@@ -146,16 +146,17 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
     }
 }
 
-template <typename T, int N1, int N2, int W>
-__global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads)) void k_zpass(ZArgs<T> A)
+// MW: minimum waves per SIMD the register allocation must allow (1 = no bound).
+template <typename T, int N1, int N2, int W, int MW>
+__global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads), MW) void k_zpass(ZArgs<T> A)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     zpass_body<T, N1, N2, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 // Batched: blockIdx.y selects a replica whose arguments come from a table.
-template <typename T, int N1, int N2, int W>
-__global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads)) void k_zpass_batch(const ZArgs<T>* __restrict__ descs)
+template <typename T, int N1, int N2, int W, int MW>
+__global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads), MW) void k_zpass_batch(const ZArgs<T>* __restrict__ descs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const ZArgs<T> A = descs[blockIdx.y];
@@ -224,10 +225,7 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
         if (act) sfor<0, N1>([&](auto I) { X[base + decltype(I)::value * step] = a[decltype(I)::value]; });
     };
     // one array: diffuse, [capture], [multiply by e2 = E4^2, diffuse again]
-    auto run = [&](cx<T>* X, const SOps<T>& op, const cx<T>(&e2)[N1], bool have_e2) {
-        if (!op.g1) return;
-        cx<T> a[N1];
-        ldX(X, a);
+    auto run_on = [&](cx<T>* X, cx<T>(&a)[N1], const SOps<T>& op, const cx<T>(&e2)[N1], bool have_e2) {
         diffuse<N1, N2>(a, t, sh, lay, op.g1);
         if (op.acap) stX(op.acap, a);
         if (AXIS == 0 && op.e) {  // field multiplies happen only in the x pass
@@ -244,7 +242,23 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
         }
         stX(X, a);
     };
+    auto run = [&](cx<T>* X, const SOps<T>& op, const cx<T>(&e2)[N1], bool have_e2) {
+        if (!op.g1) return;
+        cx<T> a[N1];
+        ldX(X, a);
+        run_on(X, a, op, e2, have_e2);
+    };
     cx<T> e2[N1];
+    if (AXIS == 1 && N1 * sizeof(cx<T>) <= 256 && A.opU.g1 && A.opV.g1) {
+        // y pass on both arrays: V's loads are issued before U's transform so
+        // that their latency hides behind it (where the second array still fits
+        // the registers of two waves per SIMD)
+        cx<T> v[N1];
+        ldX(A.V, v);
+        run(A.U, A.opU, e2, false);
+        run_on(A.V, v, A.opV, e2, false);
+        return;
+    }
     if (AXIS == 0 && A.opU.g1 && A.opV.g1 && A.opU.e && A.opU.e == A.opV.e) {
         // both arrays take the same field table: read it once
         ldX(A.opU.e, e2);
@@ -258,15 +272,15 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
 }
 
 // AXIS (0 = x, 1 = y) also names the kernel, so profiles tell the passes apart.
-template <typename T, int N1, int N2, int AXIS, int W>
-__global__ __launch_bounds__((SShape<T, N2, W>::kThreads)) void k_spass(SArgs<T> A)
+template <typename T, int N1, int N2, int AXIS, int W, int MW>
+__global__ __launch_bounds__((SShape<T, N2, W>::kThreads), MW) void k_spass(SArgs<T> A)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     spass_body<T, N1, N2, AXIS, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
-template <typename T, int N1, int N2, int AXIS, int W>
-__global__ __launch_bounds__((SShape<T, N2, W>::kThreads)) void k_spass_batch(const SArgs<T>* __restrict__ descs)
+template <typename T, int N1, int N2, int AXIS, int W, int MW>
+__global__ __launch_bounds__((SShape<T, N2, W>::kThreads), MW) void k_spass_batch(const SArgs<T>* __restrict__ descs)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const SArgs<T> A = descs[blockIdx.y];
@@ -292,44 +306,47 @@ __global__ __launch_bounds__((SShape<T, N2, W>::kThreads)) void k_spass_batch(co
     X(192, 24, 8)         \
     X(256, 16, 16)
 
-// Kernel variants per axis length, as (N, variant, N1, N2, W): variant 0 is the
-// default split and tile; the others widen the workgroup tile (W = 2) or use
-// another radix split N = N1 * N2.  Variant 0 compiles with the rest of the
-// library; the others sit in their own translation units.
-#define PFT_AXIS_VARIANTS0(X) \
-    X(8, 0, 8, 1, 1)          \
-    X(12, 0, 12, 1, 1)        \
-    X(16, 0, 16, 1, 1)        \
-    X(20, 0, 20, 1, 1)        \
-    X(24, 0, 12, 2, 1)        \
-    X(32, 0, 16, 2, 1)        \
-    X(40, 0, 20, 2, 1)        \
-    X(48, 0, 12, 4, 1)        \
-    X(64, 0, 16, 4, 1)        \
-    X(80, 0, 20, 4, 1)        \
-    X(96, 0, 24, 4, 1)        \
-    X(128, 0, 16, 8, 1)       \
-    X(192, 0, 24, 8, 1)       \
-    X(256, 0, 16, 16, 1)
-#define PFT_AXIS_VARIANTS_ALT(X) \
-    X(16, 1, 16, 1, 2)           \
-    X(16, 2, 4, 4, 1)            \
-    X(24, 1, 12, 2, 2)           \
-    X(32, 1, 16, 2, 2)           \
-    X(32, 2, 8, 4, 1)            \
-    X(40, 1, 20, 2, 2)           \
-    X(48, 1, 12, 4, 2)           \
-    X(64, 1, 16, 4, 2)           \
-    X(64, 2, 8, 8, 1)            \
-    X(96, 1, 24, 4, 2)           \
-    X(128, 1, 16, 8, 2)          \
-    X(256, 1, 16, 16, 2)
+// Kernel variants per axis length, as (N, variant, N1, N2, W, MW): variant 0 is
+// the default split and tile; the others widen the workgroup tile (W = 2), use
+// another radix split N = N1 * N2, or bound the registers so that MW = 2 waves
+// fit on each SIMD.  Variant 0 compiles with the rest of the library; the
+// others sit in their own translation units.
+#define PFT_AXIS_VARIANTS0(X)     \
+    X(8, 0, 8, 1, 1, 1)           \
+    X(12, 0, 12, 1, 1, 1)         \
+    X(16, 0, 16, 1, 1, 1)         \
+    X(20, 0, 20, 1, 1, 1)         \
+    X(24, 0, 12, 2, 1, 1)         \
+    X(32, 0, 16, 2, 1, 1)         \
+    X(40, 0, 20, 2, 1, 1)         \
+    X(48, 0, 12, 4, 1, 1)         \
+    X(64, 0, 16, 4, 1, 1)         \
+    X(80, 0, 20, 4, 1, 1)         \
+    X(96, 0, 24, 4, 1, 1)         \
+    X(128, 0, 16, 8, 1, 1)        \
+    X(192, 0, 24, 8, 1, 1)        \
+    X(256, 0, 16, 16, 1, 1)
+#define PFT_AXIS_VARIANTS_ALT(X)  \
+    X(16, 1, 16, 1, 2, 1)         \
+    X(16, 2, 4, 4, 1, 1)          \
+    X(24, 1, 12, 2, 2, 1)         \
+    X(32, 1, 16, 2, 2, 1)         \
+    X(32, 2, 8, 4, 1, 1)          \
+    X(40, 1, 20, 2, 2, 1)         \
+    X(48, 1, 12, 4, 2, 1)         \
+    X(64, 1, 16, 4, 2, 1)         \
+    X(64, 2, 8, 8, 1, 1)          \
+    X(64, 3, 16, 4, 1, 2)         \
+    X(96, 1, 24, 4, 2, 1)         \
+    X(128, 1, 16, 8, 2, 1)        \
+    X(128, 2, 16, 8, 1, 2)        \
+    X(256, 1, 16, 16, 2, 1)
 #define PFT_AXIS_VARIANTS(X) PFT_AXIS_VARIANTS0(X) PFT_AXIS_VARIANTS_ALT(X)
 
 // Shape of variant v of axis length n; false if there is none.
 inline bool axis_variant(int n, int v, int* n1, int* n2, int* w)
 {
-#define PFT_CASE(N, VID, A1, A2, WW)  \
+#define PFT_CASE(N, VID, A1, A2, WW, MW) \
     if (n == N && v == VID) {         \
         *n1 = A1;                     \
         *n2 = A2;                     \
