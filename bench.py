@@ -87,13 +87,16 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     # timed region: exactly `steps` evaluations between two events, both sweeps
     # running concurrently on two streams (the library's default)
     ms = timed(steps)
-    ms_axis = None
+    by_schedule = None
     if fused:
-        # the same with the axis schedule (four passes per step), for comparison
-        ctx.pft_set_fused_planes(False)
-        evaluate()
-        ms_axis = timed(steps)
-        ctx.pft_set_fused_planes(True)
+        # the same with the other schedules, for comparison: axis passes only
+        # (four per step), and fused yz passes in the conjugate sweep only
+        by_schedule = {{1: "fused", 2: "fused-conjugate-sweep"}[fused]: ms}
+        for mode, name in ((0, "axis"), (3 - fused, {1: "fused", 2: "fused-conjugate-sweep"}[3 - fused])):
+            ctx.pft_set_fused_planes(mode)
+            evaluate()
+            by_schedule[name] = timed(steps)
+        ctx.pft_set_fused_planes(fused)
         evaluate()
     # the same with both sweeps on one stream, for comparison
     ctx.pft_set_concurrent_sweeps(False)
@@ -130,9 +133,10 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     bytes_eval = sum(v[2] for v in prof.values()) / steps
     roof["aggregate_GB_s"] = round(bytes_eval / (ms * 1e-3) / 1e9, 1)
     out = {"value": rate, "ms_per_step": ms, "ms_per_step_one_stream": ms_single, "roofline": roof,
-           "kernels": breakdown, "Q": [Qv.real, Qv.imag], "schedule": "fused-yz" if fused else "axis"}
-    if ms_axis is not None:
-        out["ms_per_step_axis_schedule"] = ms_axis
+           "kernels": breakdown, "Q": [Qv.real, Qv.imag],
+           "schedule": {0: "axis", 1: "fused", 2: "fused-conjugate-sweep"}[fused]}
+    if by_schedule is not None:
+        out["ms_per_step_by_schedule"] = by_schedule
     return out
 
 
@@ -313,8 +317,8 @@ def main():
         "kernels": main_["kernels"],
         "schedule": main_["schedule"],
     }
-    if "ms_per_step_axis_schedule" in main_:
-        line["ms_per_step_axis_schedule"] = main_["ms_per_step_axis_schedule"]
+    if "ms_per_step_by_schedule" in main_:
+        line["ms_per_step_by_schedule"] = main_["ms_per_step_by_schedule"]
     if tuned is not None:
         line["kernel_variants"] = tuned
     if batched is not None:
@@ -324,8 +328,8 @@ def main():
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],
                         "dtype": "f32 propagators, f64 sums", "roofline": res["f32"]["roofline"],
                         "kernels": res["f32"]["kernels"], "schedule": res["f32"]["schedule"]}
-        if "ms_per_step_axis_schedule" in res["f32"]:
-            line["fp32"]["ms_per_step_axis_schedule"] = res["f32"]["ms_per_step_axis_schedule"]
+        if "ms_per_step_by_schedule" in res["f32"]:
+            line["fp32"]["ms_per_step_by_schedule"] = res["f32"]["ms_per_step_by_schedule"]
     print(json.dumps(line))
 
 

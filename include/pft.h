@@ -105,11 +105,15 @@ pft_status pft_set_concurrent_sweeps(pft_ctx* ctx, int32_t on);
  * float: up to 128 x 128; complex double: up to 96 x 96) the y, z, y passes
  * between two x passes fuse into one pass per x-plane, and a step moves 11
  * instead of 17 arrays.  New contexts use the fused schedule where it exists.
- * The schedule applies to pft_propagate, pft_cl_step and pft_apply_step; the
- * reverse mode (pft_adjoint) and batches always use the axis schedule.
- * on = 1 without a fused kernel for the shape: PFT_E_UNSUPPORTED (schedule
- * unchanged).  pft_fused_planes returns 1 / 0 for the current schedule, -1
- * for NULL. */
+ * The schedule applies to pft_propagate, pft_cl_step and pft_apply_step, and
+ * batches use the fused one for every replica group whose shape has it; the
+ * reverse mode (pft_adjoint) always uses the axis schedule.
+ * on = 2 fuses only the conjugate (q-dagger) sweep of pft_propagate, whose
+ * on-chip-bound plane passes then share the device with the forward sweep's
+ * memory-bound axis passes when the two sweeps run concurrently.
+ * on = 1 or 2 without a fused kernel for the shape: PFT_E_UNSUPPORTED
+ * (schedule unchanged); other values: PFT_E_INVALID.  pft_fused_planes returns
+ * the current setting (0, 1, 2), -1 for NULL. */
 pft_status pft_set_fused_planes(pft_ctx* ctx, int32_t on);
 int32_t pft_fused_planes(const pft_ctx* ctx);
 

@@ -263,11 +263,13 @@ class Context:
     def pft_set_concurrent_sweeps(self, on: bool):
         self._check(load().pft_set_concurrent_sweeps(self._h, int(bool(on))))
 
-    def pft_set_fused_planes(self, on: bool):
-        self._check(load().pft_set_fused_planes(self._h, int(bool(on))))
+    def pft_set_fused_planes(self, on):
+        """0 / False: axis schedule; 1 / True: fused yz passes in both sweeps;
+        2: in the conjugate sweep only."""
+        self._check(load().pft_set_fused_planes(self._h, int(on)))
 
-    def pft_fused_planes(self) -> bool:
-        return load().pft_fused_planes(self._h) == 1
+    def pft_fused_planes(self) -> int:
+        return load().pft_fused_planes(self._h)
 
     def pft_set_variant(self, axis: int, variant: int):
         self._check(load().pft_set_variant(self._h, axis, variant))

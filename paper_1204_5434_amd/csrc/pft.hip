@@ -784,6 +784,7 @@ struct pft_ctx {
     int maxN = 0;
     int var[3] = {0, 0, 0};           // kernel variant of each axis pass (x, y, z)
     bool fused = false;               // sweeps use the fused yz-plane pass (square yz-plane in LDS)
+    bool fused_conj_only = false;     // ... only the conjugate sweep (the forward one runs axis passes)
     size_t elem = 0;                  // bytes per propagator value
     // device buffers
     void* qs = nullptr;
@@ -1056,7 +1057,7 @@ template <typename T>
 pft_status sweep(pft_ctx* c, bool backward, void* store, const Work& w = Work())
 {
     auto stepj = [&](int i) { return backward ? c->K - 1 - i : i; };
-    if (c->fused) {
+    if (c->fused && (backward || !c->fused_conj_only)) {
         // two passes per step: X, then yz completing it and starting the next
         pft_status s = yzpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0), w);
         if (s) return s;
@@ -1492,6 +1493,33 @@ pft::ZArgs<T> zargs(const pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T
 }
 
 template <typename T>
+pft::PArgs<T> pargs(const pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout)
+{
+    pft::PArgs<T> a{};
+    a.nplanes = c->p.nx;
+    a.U = static_cast<cx<T>*>(c->U);
+    a.V = static_cast<cx<T>*>(c->V);
+    a.qin = qin;
+    a.qout = qout;
+    a.scheme = c->p.scheme;
+    a.has_prev = prev >= 0;
+    a.has_next = next >= 0;
+    if (prev >= 0) {
+        a.Ep = etab<T>(c, c->kind[prev]);
+        a.gyh_p = gptr<T>(c, c->hid[prev], 0, 1);
+        a.gzh_p = gptr<T>(c, c->hid[prev], 0, 2);
+    }
+    if (next >= 0) {
+        a.En = etab<T>(c, c->kind[next]);
+        a.gzh_n = gptr<T>(c, c->hid[next], 0, 2);
+        a.gzf_n = gptr<T>(c, c->hid[next], 1, 2);
+        a.gyh_n = gptr<T>(c, c->hid[next], 0, 1);
+        a.gyf_n = gptr<T>(c, c->hid[next], 1, 1);
+    }
+    return a;
+}
+
+template <typename T>
 pft::SArgs<T> sargs(const pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV)
 {
     pft::SArgs<T> a{};
@@ -1572,9 +1600,10 @@ struct BatchGroup {
     int npass = 0;               // strided passes per step (3 or 2)
     int sp_axis[3] = {0, 0, 0};
     int var[3] = {0, 0, 0};      // kernel variants (x, y, z) of the group's grid
+    bool fused = false;          // fused yz-plane schedule: zd holds PArgs, sd the x passes only
     hipStream_t s = nullptr;
     hipEvent_t done = nullptr;
-    void* zd = nullptr;          // [dir 2][pos maxK+1][R] ZArgs
+    void* zd = nullptr;          // [dir 2][pos maxK+1][R] ZArgs (PArgs when fused)
     void* sd = nullptr;          // [dir 2][pos maxK][npass][R] SArgs
     void* jobs = nullptr;        // job tables for the small kernels
     size_t off_tab = 0, off_sum = 0, off_fin = 0, off_dens = 0, off_ham = 0, off_upd = 0;
@@ -1648,7 +1677,8 @@ template <typename T>
 pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
 {
     const int R = (int)g.reps.size();
-    std::vector<pft::ZArgs<T>> zd((size_t)2 * (g.maxK + 1) * R);
+    std::vector<pft::ZArgs<T>> zd(g.fused ? 0 : (size_t)2 * (g.maxK + 1) * R);
+    std::vector<pft::PArgs<T>> pd(g.fused ? (size_t)2 * (g.maxK + 1) * R : 0);
     std::vector<pft::SArgs<T>> sd((size_t)2 * g.maxK * g.npass * R);
     for (int dir = 0; dir < 2; ++dir)
         for (int ri = 0; ri < R; ++ri) {
@@ -1657,14 +1687,16 @@ pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
             auto stepj = [&](int i) { return dir ? K - 1 - i : i; };
             void* store = dir ? c->qds : c->qs;
             for (int p = 0; p <= g.maxK; ++p) {
-                const int i = p - 1;  // Z at position p completes step i and starts step i + 1
-                pft::ZArgs<T>& z = zd[((size_t)dir * (g.maxK + 1) + p) * R + ri];
-                if (i >= K) {
-                    z.skip = 1;
-                    continue;
+                const int i = p - 1;  // Z (or yz) at position p completes step i and starts step i + 1
+                const size_t at = ((size_t)dir * (g.maxK + 1) + p) * R + ri;
+                const int prev = i >= 0 ? stepj(i) : -1, next = i + 1 < K ? stepj(i + 1) : -1;
+                if (g.fused) {
+                    if (i >= K) pd[at].skip = 1;
+                    else pd[at] = pargs<T>(c, prev, next, nullptr, slice<T>(store, c, i + 1));
+                } else {
+                    if (i >= K) zd[at].skip = 1;
+                    else zd[at] = zargs<T>(c, prev, next, nullptr, slice<T>(store, c, i + 1));
                 }
-                z = zargs<T>(c, i >= 0 ? stepj(i) : -1, i + 1 < K ? stepj(i + 1) : -1, nullptr,
-                             slice<T>(store, c, i + 1));
             }
             for (int p = 0; p < g.maxK; ++p) {
                 int ax[3];
@@ -1676,13 +1708,15 @@ pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
                         d.skip = 1;
                         continue;
                     }
-                    d = sa[k];
+                    d = g.fused ? sa[1] : sa[k];  // fused: the x pass alone
                 }
             }
         }
-    PFT_BHIP(b, hipMalloc(&g.zd, zd.size() * sizeof(zd[0])));
+    const size_t zbytes = g.fused ? pd.size() * sizeof(pd[0]) : zd.size() * sizeof(zd[0]);
+    PFT_BHIP(b, hipMalloc(&g.zd, zbytes));
     PFT_BHIP(b, hipMalloc(&g.sd, std::max<size_t>(1, sd.size()) * sizeof(pft::SArgs<T>)));
-    PFT_BHIP(b, hipMemcpy(g.zd, zd.data(), zd.size() * sizeof(zd[0]), hipMemcpyHostToDevice));
+    PFT_BHIP(b, hipMemcpy(g.zd, g.fused ? (const void*)pd.data() : (const void*)zd.data(), zbytes,
+                          hipMemcpyHostToDevice));
     if (!sd.empty()) PFT_BHIP(b, hipMemcpy(g.sd, sd.data(), sd.size() * sizeof(sd[0]), hipMemcpyHostToDevice));
     return PFT_OK;
 }
@@ -1782,15 +1816,22 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update)
     const int n_ax[2] = {g.nx, g.ny};
     const int64_t ncols[2] = {(int64_t)g.ny * g.nz, g.nz};
     const int nslabs[2] = {1, g.nx};
+    const pft::PArgs<T>* pd = static_cast<const pft::PArgs<T>*>(g.zd);
+    // the z pass, or the fused yz pass, at sweep position p
+    auto zlaunch = [&](int dir, int p) -> hipError_t {
+        const size_t at = ((size_t)dir * (g.maxK + 1) + p) * R;
+        if (g.fused) return pft::launch_yzpass_batch<T>(g.ny, g.nx, pd + at, R, s);
+        return pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + at, R, s);
+    };
     for (int dir = 0; dir < 2; ++dir) {
-        PFT_BHIP(b, pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + ((size_t)dir * (g.maxK + 1) + 0) * R, R, s));
+        PFT_BHIP(b, zlaunch(dir, 0));
         for (int p = 0; p < g.maxK; ++p) {
             for (int k = 0; k < g.npass; ++k) {
                 const int ax = g.sp_axis[k];
                 PFT_BHIP(b, pft::launch_spass_batch<T>(ax, n_ax[ax], g.var[ax], ncols[ax], nslabs[ax],
                                                        sd + (((size_t)dir * g.maxK + p) * g.npass + k) * R, R, s));
             }
-            PFT_BHIP(b, pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + ((size_t)dir * (g.maxK + 1) + p + 1) * R, R, s));
+            PFT_BHIP(b, zlaunch(dir, p + 1));
         }
     }
     hipLaunchKernelGGL((k_sum_partials_batch<T>), dim3(64, R), dim3(kRedThreads), 0, s,
@@ -2048,13 +2089,15 @@ static bool fused_supported(const pft_params& p)
 pft_status pft_set_fused_planes(pft_ctx* c, int32_t on)
 {
     if (!c) return PFT_E_INVALID;
+    if (on < 0 || on > 2) return c->fail(PFT_E_INVALID, "schedule %d is not 0, 1 or 2", on);
     if (on && !fused_supported(c->p))
         return c->fail(PFT_E_UNSUPPORTED, "no fused yz-plane pass for a %d x %d plane in this precision", c->p.ny, c->p.nz);
     c->fused = on != 0;
+    c->fused_conj_only = on == 2;
     return PFT_OK;
 }
 
-int32_t pft_fused_planes(const pft_ctx* c) { return c ? (c->fused ? 1 : 0) : -1; }
+int32_t pft_fused_planes(const pft_ctx* c) { return c ? (c->fused ? (c->fused_conj_only ? 2 : 1) : 0) : -1; }
 
 static pft_status create_ctx(const pft_params* params, void* hip_stream, bool dual, pft_ctx** out)
 {
@@ -2370,9 +2413,15 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
             g->nx = p.nx;
             g->ny = p.ny;
             g->nz = p.nz;
-            g->npass = p.scheme == PFT_RQM4 ? 3 : 2;
-            const int ax3[3] = {1, 0, 1};
-            for (int k = 0; k < 3; ++k) g->sp_axis[k] = ax3[k];
+            g->fused = b->ctx[r]->fused;
+            if (g->fused) {
+                g->npass = 1;  // the x pass; the y and z work runs in the yz pass
+                g->sp_axis[0] = 0;
+            } else {
+                g->npass = p.scheme == PFT_RQM4 ? 3 : 2;
+                const int ax3[3] = {1, 0, 1};
+                for (int k = 0; k < 3; ++k) g->sp_axis[k] = ax3[k];
+            }
         }
         g->reps.push_back(r);
         for (int a = 0; a < 3; ++a) g->var[a] = b->ctx[g->reps[0]]->var[a];

@@ -44,7 +44,6 @@ def test_batch_evaluate_matches_single_and_oracle(orc, prec):
     for r, w in enumerate(reps):
         print("replica", r, w.n, w.ns, round(w.f, 3), flush=True)
         ctx = B.Context(params[r])
-        ctx.pft_set_fused_planes(False)  # batches run the axis schedule: same kernels
         out = ctx.evaluate(wp[r], wm[r])
         assert np.abs(host(pa[r]) - host(out["phiA"])).max() <= 1e-13
         assert abs(host(Q)[r] - host(out["Q"])[0]) <= 1e-13 * abs(host(out["Q"])[0])
@@ -72,7 +71,6 @@ def test_batch_graph_steps_match_single_steps():
     bat.pft_batch_sync()
     for r, w in enumerate(reps):
         ctx = B.Context(params[r])
-        ctx.pft_set_fused_planes(False)
         a, b = dev(fields[r][0]), dev(fields[r][1])
         Qs, Hs = [], []
         Qt = torch.empty(1, dtype=torch.complex128, device=DEV)

@@ -63,13 +63,16 @@ def test_fused_schedule_matches_oracle(orc, prec, N):
     ctx = B.Context(B.Params(*n, *L, ns, f, chiN, C, prec, scheme))
     assert ctx.pft_fused_planes()  # the default where the kernel exists
     fused = evaluate(ctx, wp, wm)
+    ctx.pft_set_fused_planes(2)
+    assert ctx.pft_fused_planes() == 2
+    conj = evaluate(ctx, wp, wm)
     ctx.pft_set_fused_planes(False)
     assert not ctx.pft_fused_planes()
     axis = evaluate(ctx, wp, wm)
     assert ctx.pft_status_flags() == 0
     ctx.close()
     V = np.prod(L)
-    for got in (fused, axis):
+    for got in (fused, conj, axis):
         if prec == B.PFT_C128:
             for key in ("phiA", "phiB"):
                 assert np.abs(got[key] - ref[key]).max() <= 1e-10, key
@@ -84,6 +87,7 @@ def test_fused_schedule_matches_oracle(orc, prec, N):
     tol = 1e-12 if prec == B.PFT_C128 else 1e-5
     scale = np.abs(axis["phiA"]).max()
     assert np.abs(fused["phiA"] - axis["phiA"]).max() <= tol * scale
+    assert np.abs(conj["phiA"] - axis["phiA"]).max() <= tol * scale
 
 
 @pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
@@ -118,8 +122,12 @@ def test_fused_unsupported_shapes():
     for n, prec in (((16, 16, 32), B.PFT_C128), ((8, 128, 128), B.PFT_C128), ((8, 256, 256), B.PFT_C64)):
         ctx = B.Context(B.Params(*n, 1.0, 1.0, 1.0, 4, 0.5, 10.0, 1.0, prec, 0))
         assert not ctx.pft_fused_planes()
+        for mode in (1, 2):
+            with pytest.raises(B.PftError) as e:
+                ctx.pft_set_fused_planes(mode)
+            assert e.value.status == B.PFT_E_UNSUPPORTED
         with pytest.raises(B.PftError) as e:
-            ctx.pft_set_fused_planes(True)
-        assert e.value.status == B.PFT_E_UNSUPPORTED
+            ctx.pft_set_fused_planes(3)
+        assert e.value.status == B.PFT_E_INVALID
         assert not ctx.pft_fused_planes()
         ctx.close()
