@@ -320,7 +320,9 @@ __device__ __forceinline__ void dft(cx<T>* v)
 // Forward: an N1-point DFT in registers over n1, the twiddle W_N^{t k1}, an
 // LDS transpose, then N1/N2 DFTs of N2 points per lane give X[k1 + N1 k2] for
 // the lane's k1 = t + N2 i.  The factor g is applied there, and the inverse
-// retraces the same steps, so the spectrum never needs natural order.
+// retraces the same steps, so the spectrum never needs natural order.  Two
+// barriers per direction change suffice: the rows k1 of the stage-two matrix
+// belong to one lane each.
 //
 // lay(k1, n2) maps an element of the exchanged N1 x N2 matrix of this lane's
 // line to its LDS slot.  Every lane of the workgroup must call diffuse()
@@ -346,24 +348,21 @@ __device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict
         __syncthreads();
         sfor<0, N1>([&](auto K1) { sh[lay(decltype(K1)::value, t)] = a[decltype(K1)::value]; });
         __syncthreads();
-        cx<T> b[NB][N2];
+        // stage two: row k1 of the exchanged matrix is read and written back by
+        // its owning lane only, so each row goes back as soon as it is done
         sfor<0, NB>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const int k1 = t + N2 * i;
-            sfor<0, N2>([&](auto M2) { b[i][decltype(M2)::value] = sh[lay(k1, decltype(M2)::value)]; });
-            dft<N2, false>(b[i]);
+            cx<T> b[N2];
+            sfor<0, N2>([&](auto M2) { b[decltype(M2)::value] = sh[lay(k1, decltype(M2)::value)]; });
+            dft<N2, false>(b);
             sfor<0, N2>([&](auto K2) {
                 constexpr int k2 = decltype(K2)::value;
                 const T gk = g[k1 + N1 * k2];
-                b[i][k2] = gk * b[i][k2];
+                b[k2] = gk * b[k2];
             });
-            dft<N2, true>(b[i]);
-        });
-        __syncthreads();
-        sfor<0, NB>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            const int k1 = t + N2 * i;
-            sfor<0, N2>([&](auto M2) { sh[lay(k1, decltype(M2)::value)] = b[i][decltype(M2)::value]; });
+            dft<N2, true>(b);
+            sfor<0, N2>([&](auto M2) { sh[lay(k1, decltype(M2)::value)] = b[decltype(M2)::value]; });
         });
         __syncthreads();
         sfor<0, N1>([&](auto K1) { a[decltype(K1)::value] = sh[lay(decltype(K1)::value, t)]; });
