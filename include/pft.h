@@ -104,7 +104,10 @@ pft_status pft_set_concurrent_sweeps(pft_ctx* ctx, int32_t on);
  * ny == nz and one yz-plane fits in the 160 KB LDS of a compute unit (complex
  * float: up to 128 x 128; complex double: up to 96 x 96) the y, z, y passes
  * between two x passes fuse into one pass per x-plane, and a step moves 11
- * instead of 17 arrays.  New contexts use the fused schedule where it exists.
+ * instead of 17 arrays.  New contexts use the fused schedule where it exists
+ * and its compiled kernel spills at most 256 bytes per lane (on gfx950 every
+ * such plane except complex double 96 x 96, measured slower than the axis
+ * schedule); pft_set_fused_planes overrides the choice.
  * The schedule applies to pft_propagate, pft_cl_step and pft_apply_step, and
  * batches use the fused one for every replica group whose shape has it; the
  * reverse mode (pft_adjoint) always uses the axis schedule.

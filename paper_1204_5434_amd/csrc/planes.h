@@ -267,6 +267,11 @@ __global__ __launch_bounds__((PShape<T, N1, N2>::kThreads)) void k_yzpass_batch(
 template <typename T>
 bool plane_supported(int n);
 
+// Private (register spill) bytes per lane of the compiled fused kernel for side
+// n, -1 if there is none or the runtime cannot say.
+template <typename T>
+int plane_private_bytes(int n);
+
 // Launch over nx planes (a.nplanes), or over nrep replicas of one shape.
 template <typename T>
 hipError_t launch_yzpass(int n, const PArgs<T>& a, hipStream_t s);

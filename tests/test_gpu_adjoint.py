@@ -110,7 +110,7 @@ def test_gradient_state_fd_and_force():
     gwp, gwm = dev(wp), dev(wm)
     gp, gm, dL, H0 = gpu_adjoint(ctx, gwp, gwm, kc=11)
     Hbuf = torch.empty(1, dtype=torch.complex128, device=DEV)
-    assert ctx.pft_fused_planes()
+    ctx.pft_set_fused_planes(1)
     ctx.pft_propagate(gwp, gwm)
     ctx.pft_hamiltonian(gwp, gwm, Hbuf)
     assert abs(complex(host(Hbuf)[0]) - H0) <= 1e-12 * abs(H0)

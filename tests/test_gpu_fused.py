@@ -61,7 +61,11 @@ def test_fused_schedule_matches_oracle(orc, prec, N):
     wp, wm = rand_fields(n, 100 + N)
     ref = orc.evaluate(orc.Params(*n, *L, ns, f, chiN, C, scheme, False), wp, wm)
     ctx = B.Context(B.Params(*n, *L, ns, f, chiN, C, prec, scheme))
-    assert ctx.pft_fused_planes()  # the default where the kernel exists
+    default = ctx.pft_fused_planes()
+    assert default in (0, 1)
+    if N <= 64:
+        assert default == 1  # spill-free plane kernels are the default
+    ctx.pft_set_fused_planes(1)
     fused = evaluate(ctx, wp, wm)
     ctx.pft_set_fused_planes(2)
     assert ctx.pft_fused_planes() == 2
