@@ -19,6 +19,7 @@
 // transform direction), so each pass reads and writes each array once.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "fft.h"
@@ -26,6 +27,25 @@
 namespace pft {
 
 enum { kSchemeRQM4 = 0, kSchemeSplit2 = 1 };
+
+// Profiling hook: when set, the next launch through PFT_LAUNCH records this
+// event pair as part of its own dispatch (start and end of the kernel, no
+// queue gaps) and clears it.  Host-side state, one per host thread.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+#define PFT_LAUNCH(kernel, grid, block, shmem, stream, ...)                                              \
+    do {                                                                                               \
+        if (::pft::g_launch_events.start) {                                                            \
+            const ::pft::LaunchEvents ev_ = ::pft::g_launch_events;                                    \
+            ::pft::g_launch_events = ::pft::LaunchEvents{};                                            \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ev_.start, ev_.stop, 0, __VA_ARGS__); \
+        } else {                                                                                       \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                       \
+        }                                                                                              \
+    } while (0)
 
 // ------------------------------------------------------------------ z pass --
 template <typename T>

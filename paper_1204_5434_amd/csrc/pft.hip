@@ -20,6 +20,10 @@
 
 using pft::cx;
 
+namespace pft {
+thread_local LaunchEvents g_launch_events;
+}
+
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
@@ -845,13 +849,17 @@ bool aligned16(const void* p) { return p && (reinterpret_cast<uintptr_t>(p) & 15
 
 // Brackets one launch with a pair of events on the context stream while
 // profiling is on; records the launch's kernel kind and algorithmic bytes.
+// With `single` the scope holds exactly one launch made through PFT_LAUNCH,
+// which records the pair inside its own dispatch (kernel start to end);
+// otherwise the pair is recorded on the stream around the scope's launches.
 struct ProfScope {
     pft_ctx* c;
     size_t i = 0;
     bool on;
     hipStream_t st;
-    ProfScope(pft_ctx* ctx, int kind, double bytes, hipStream_t s = nullptr)
-        : c(ctx), on(ctx->prof), st(s ? s : ctx->stream)
+    bool single;
+    ProfScope(pft_ctx* ctx, int kind, double bytes, hipStream_t s = nullptr, bool one_launch = false)
+        : c(ctx), on(ctx->prof), st(s ? s : ctx->stream), single(one_launch)
     {
         if (!on) return;
         i = c->ev_used;
@@ -870,11 +878,24 @@ struct ProfScope {
         c->ev_kind[i] = kind;
         c->ev_bytes[i] = bytes;
         c->ev_used = i + 1;
-        (void)hipEventRecord(c->ev[2 * i], st);
+        if (single)
+            pft::g_launch_events = pft::LaunchEvents{c->ev[2 * i], c->ev[2 * i + 1]};
+        else
+            (void)hipEventRecord(c->ev[2 * i], st);
     }
     ~ProfScope()
     {
-        if (on) (void)hipEventRecord(c->ev[2 * i + 1], st);
+        if (!on) return;
+        if (single) {
+            if (pft::g_launch_events.start) {
+                // the launch did not take the pair (it failed): keep the pair valid
+                pft::g_launch_events = pft::LaunchEvents{};
+                (void)hipEventRecord(c->ev[2 * i], st);
+                (void)hipEventRecord(c->ev[2 * i + 1], st);
+            }
+        } else {
+            (void)hipEventRecord(c->ev[2 * i + 1], st);
+        }
     }
 };
 
@@ -938,7 +959,7 @@ pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout, 
     if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
     if (hcap) bytes += E;
     hipStream_t st = w.stream ? w.stream : c->stream;
-    ProfScope ps(c, PFT_K_ZPASS, bytes, st);
+    ProfScope ps(c, PFT_K_ZPASS, bytes, st, true);
     PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], a, st));
     return PFT_OK;
 }
@@ -959,7 +980,7 @@ pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV, const
     if (opU.g1 && opU.e) bytes += E;
     if (opV.g1 && opV.e && !(opU.g1 && opU.e == opV.e)) bytes += E;
     hipStream_t st = w.stream ? w.stream : c->stream;
-    ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes, st);
+    ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes, st, true);
     const int64_t nynz = (int64_t)c->p.ny * c->p.nz;
     if (axis == 0) {
         a.S = nynz;
@@ -1011,7 +1032,7 @@ pft_status yzpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout,
     if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
     if (hcap) bytes += E;
     hipStream_t st = w.stream ? w.stream : c->stream;
-    ProfScope ps(c, PFT_K_YZPASS, bytes, st);
+    ProfScope ps(c, PFT_K_YZPASS, bytes, st, true);
     PFT_HIP(c, pft::launch_yzpass<T>(c->p.ny, a, st));
     return PFT_OK;
 }
@@ -1093,8 +1114,8 @@ pft_status field_tables_t(pft_ctx* c, const double* wp, const double* wm)
     d.blk[3] = 1; d.a[3] = c->hval[2] / 4;
     if (c->K == c->p.ns) d.n = 2;  // no junction sub-steps
     {
-        ProfScope ps(c, PFT_K_TABLES, (32.0 + d.n * (double)c->elem) * (double)c->M);
-        hipLaunchKernelGGL((k_field_tables<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
+        ProfScope ps(c, PFT_K_TABLES, (32.0 + d.n * (double)c->elem) * (double)c->M, nullptr, true);
+        PFT_LAUNCH((k_field_tables<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
                        reinterpret_cast<const double2*>(wp), reinterpret_cast<const double2*>(wm), c->M, d,
                        static_cast<cx<T>*>(c->E));
     }
@@ -1155,8 +1176,9 @@ pft_status hamiltonian_launch(pft_ctx* c, const double* wp, const double* wm, do
 template <typename T>
 pft_status densities_t(pft_ctx* c, double* phi_a, double* phi_b, double* Q)
 {
-    ProfScope ps(c, PFT_K_DENSITY, (2.0 * (c->K + 1) * (double)c->elem + 2.0 * sizeof(double2)) * (double)c->M);
-    hipLaunchKernelGGL((k_density<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
+    ProfScope ps(c, PFT_K_DENSITY, (2.0 * (c->K + 1) * (double)c->elem + 2.0 * sizeof(double2)) * (double)c->M,
+                 nullptr, true);
+    PFT_LAUNCH((k_density<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
                        static_cast<const cx<T>*>(c->qs), static_cast<const cx<T>*>(c->qds), c->K, c->J, c->M,
                        c->tau, c->scal, reinterpret_cast<double2*>(phi_a), reinterpret_cast<double2*>(phi_b),
                        reinterpret_cast<double2*>(Q));
