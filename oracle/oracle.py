@@ -108,6 +108,12 @@ def lib():
             "or_gaussian": (None, [u64, u64, u64, i32, i64, vp]),
             "or_em_update": (None, [P, vp, vp, vp, vp, f64, f64, f64, i32, u64, u64, u64]),
             "or_adjoint": (ctypes.c_int, [P, vp, vp, vp, vp, vp]),
+            "or_edwards_propagate": (ctypes.c_int, [P, vp, vp]),
+            "or_edwards_densities": (None, [P, vp, vp, vp]),
+            "or_edwards_hamiltonian": (None, [P, f64, vp, f64, f64, vp, vp]),
+            "or_edwards_force": (None, [P, f64, vp, vp, vp]),
+            "or_edwards_em_update": (None, [P, f64, vp, vp, f64, f64, i32, u64, u64, u64]),
+            "or_edwards_evaluate": (ctypes.c_int, [P, f64, vp, vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -281,3 +287,56 @@ def adjoint(p: Params, wp, wm):
     dL = np.zeros(3, np.complex128)
     lib().or_adjoint(ctypes.byref(p._c()), _ptr(wp), _ptr(wm), _ptr(gp), _ptr(gm), _ptr(dL))
     return gp, gm, dL
+
+
+# ------------------------------------------------------------- Edwards model --
+
+def edwards_propagate(p: Params, omega):
+    """q[ns+1] in the field i*omega (one species, no junction)."""
+    omega = _cfield(omega, p.shape)
+    qs = np.empty((p.ns + 1,) + p.shape, dtype=np.complex128)
+    lib().or_edwards_propagate(ctypes.byref(p._c()), _ptr(omega), _ptr(qs))
+    return qs
+
+
+def edwards_densities(p: Params, qs):
+    """(phi, Q) with q-dagger = q."""
+    qs = _cfield(qs)
+    phi = np.empty(p.shape, np.complex128)
+    Q = np.zeros(1, np.complex128)
+    lib().or_edwards_densities(ctypes.byref(p._c()), _ptr(qs), _ptr(phi), _ptr(Q))
+    return phi, complex(Q[0])
+
+
+def edwards_hamiltonian(p: Params, B: float, omega, Q: complex):
+    omega = _cfield(omega, p.shape)
+    H = np.zeros(1, np.complex128)
+    hi = np.zeros(1, np.complex128)
+    lib().or_edwards_hamiltonian(ctypes.byref(p._c()), B, _ptr(omega), Q.real, Q.imag, _ptr(H), _ptr(hi))
+    return complex(H[0]), complex(hi[0])
+
+
+def edwards_force(p: Params, B: float, omega, phi):
+    omega, phi = _cfield(omega, p.shape), _cfield(phi, p.shape)
+    F = np.empty_like(omega)
+    lib().or_edwards_force(ctypes.byref(p._c()), B, _ptr(omega), _ptr(phi), _ptr(F))
+    return F
+
+
+def edwards_em_update(p: Params, B: float, omega, phi, dt, lam=1.0, noise=False, seed=0, replica=0, step_=0):
+    omega = np.array(omega, dtype=np.complex128, order="C", copy=True)
+    phi = _cfield(phi, p.shape)
+    lib().or_edwards_em_update(ctypes.byref(p._c()), B, _ptr(omega), _ptr(phi), dt, lam, int(bool(noise)),
+                               seed, replica, step_)
+    return omega
+
+
+def edwards_evaluate(p: Params, B: float, omega):
+    """dict with phi, Q, H, h, K."""
+    omega = _cfield(omega, p.shape)
+    phi = np.empty(p.shape, np.complex128)
+    Q = np.zeros(1, np.complex128)
+    H = np.zeros(1, np.complex128)
+    hi = np.zeros(1, np.complex128)
+    K = lib().or_edwards_evaluate(ctypes.byref(p._c()), B, _ptr(omega), _ptr(phi), _ptr(Q), _ptr(H), _ptr(hi))
+    return {"phi": phi, "Q": complex(Q[0]), "H": complex(H[0]), "h": complex(hi[0]), "K": K}

@@ -561,6 +561,106 @@ int or_evaluate(const or_params *p, const cplx *wp, const cplx *wm,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Edwards model of homopolymers in an implicit solvent, Eq. (2):           */
+/*   H[omega] = (B/2) int dx omega^2 - C V ln Q[i omega].                     */
+/* One chain species feels w = i omega along the whole contour; the chain is */
+/* symmetric, so the conjugate propagator is q itself (qd_i = q_i) and the   */
+/* density pairs node j with node K - j of the same sweep.  The contour is   */
+/* K = ns equal steps (no junction).  p->f and p->chiN are not used.          */
+/* ------------------------------------------------------------------------ */
+
+/* q_0 = 1, q_{j+1} = T_ds(q_j; i omega) (Eq. (5) with w = i omega); qs holds
+ * (ns+1)*M values.  Returns K = ns. */
+int or_edwards_propagate(const or_params *p, const cplx *omega, cplx *qs)
+{
+    const int64_t M = grid_m(p);
+    const double ds = 1.0 / p->ns;
+    cplx *w = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *work = (cplx *)malloc(sizeof(cplx) * 2 * M);
+    for (int64_t x = 0; x < M; x++) w[x] = I * omega[x];
+    for (int64_t x = 0; x < M; x++) qs[x] = 1.0;
+    for (int j = 0; j < p->ns; j++)
+        or_step(p, p->scheme, ds, w, qs + (int64_t)j * M, qs + (int64_t)(j + 1) * M, work);
+    free(w); free(work);
+    return p->ns;
+}
+
+/* Q = (1/M) sum_x q_K(x) (Eq. (4)) and phi = (1/Q) sum_j tau_j q_j q_{K-j}
+ * with the composite trapezoid weights on [0, 1] (tau_0 = tau_K = ds/2,
+ * ds elsewhere), the one-species form of Eq. (8) divided by rho_0. */
+void or_edwards_densities(const or_params *p, const cplx *qs, cplx *phi, cplx *Q)
+{
+    const int64_t M = grid_m(p);
+    const int K = p->ns;
+    const double ds = 1.0 / K;
+    cplx sum = 0.0;
+    for (int64_t x = 0; x < M; x++) sum += qs[(int64_t)K * M + x];
+    *Q = sum / (double)M;
+    #pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < M; x++) {
+        cplx a = 0.0;
+        for (int j = 0; j <= K; j++) {
+            const double tau = (j == 0 || j == K) ? 0.5 * ds : ds;
+            a += tau * qs[(int64_t)j * M + x] * qs[(int64_t)(K - j) * M + x];
+        }
+        phi[x] = a / *Q;
+    }
+}
+
+/* H = (B/2) dV sum_x omega^2 - C V log Q (Eq. (2) on the grid, principal
+ * branch); hint = H / (C V). */
+void or_edwards_hamiltonian(const or_params *p, double B, const cplx *omega, double Qre, double Qim,
+                            cplx *H, cplx *hint)
+{
+    const cplx Q = Qre + Qim * I;
+    const int64_t M = grid_m(p);
+    const double V = p->lx * p->ly * p->lz;
+    const double dV = V / (double)M;
+    cplx s = 0.0;
+    for (int64_t x = 0; x < M; x++) s += omega[x] * omega[x];
+    *H = 0.5 * B * dV * s - p->C * V * clog(Q);
+    *hint = *H / (p->C * V);
+}
+
+/* Force per unit C dV: dH/domega(x) = dV [B omega(x) + i C phi(x)], since
+ * d(-C V ln Q)/dw(x) = C dV phi(x) and dw/domega = i.  So
+ *   F = (B / C) omega + i phi. */
+void or_edwards_force(const or_params *p, double B, const cplx *omega, const cplx *phi, cplx *F)
+{
+    const int64_t M = grid_m(p);
+    for (int64_t x = 0; x < M; x++) F[x] = (B / p->C) * omega[x] + I * phi[x];
+}
+
+/* Euler-Maruyama step of Eq. (9) for omega (field 0 of the noise stream):
+ * omega <- omega - lam dt F + s xi, s^2 = 2 lam dt / (C dV). */
+void or_edwards_em_update(const or_params *p, double B, cplx *omega, const cplx *phi, double dt, double lam,
+                          int32_t noise, uint64_t seed, uint64_t replica, uint64_t step)
+{
+    const int64_t M = grid_m(p);
+    const double dV = p->lx * p->ly * p->lz / (double)M;
+    cplx *F = (cplx *)malloc(sizeof(cplx) * M);
+    double *xi = (double *)calloc(M, sizeof(double));
+    or_edwards_force(p, B, omega, phi, F);
+    if (noise) or_gaussian(seed, replica, step, 0, M, xi);
+    const double sg = noise ? sqrt(2.0 * lam * dt / (p->C * dV)) : 0.0;
+    for (int64_t x = 0; x < M; x++) omega[x] = omega[x] - lam * dt * F[x] + sg * xi[x];
+    free(F); free(xi);
+}
+
+/* One evaluation: q, Q, phi, H.  Returns K (-1 if out of memory). */
+int or_edwards_evaluate(const or_params *p, double B, const cplx *omega, cplx *phi, cplx *Q, cplx *H, cplx *hint)
+{
+    const int64_t M = grid_m(p);
+    cplx *qs = (cplx *)malloc(sizeof(cplx) * (int64_t)(p->ns + 1) * M);
+    if (!qs) return -1;
+    const int K = or_edwards_propagate(p, omega, qs);
+    or_edwards_densities(p, qs, phi, Q);
+    or_edwards_hamiltonian(p, B, omega, creal(*Q), cimag(*Q), H, hint);
+    free(qs);
+    return K;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Reverse-mode derivatives of H (Eq. (3)) through the discrete split steps. */
 /*                                                                           */
 /* Q = (1/M) 1^T q_K with q_{j+1} = T_j q_j.  Every step operator is complex- */
