@@ -140,6 +140,41 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     return out
 
 
+def edwards_run(binding, inputs, steps: int, warmup: int):
+    """Edwards homopolymer model at 128^3, Ns = 100: one forward sweep per
+    evaluation (q-dagger = q), in both working precisions."""
+    import torch
+    w = inputs.EDW128
+    om = torch.from_numpy(inputs.fields(w)[0]).to("cuda")
+    out = {"workload": w.name, "grid": list(w.n), "ns": w.ns, "B": w.extra["B"], "C": w.C,
+           "site_steps_per_evaluation": w.M * w.ns}
+    for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+        ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4,
+                                             binding.PFT_EDWARDS, w.extra["B"]))
+        phi = torch.empty(w.n, dtype=torch.complex128, device="cuda")
+        phib = torch.empty_like(phi)
+
+        def evaluate():
+            ctx.pft_propagate(om, None)
+            ctx.pft_densities(phi, phib)
+
+        for _ in range(warmup):
+            evaluate()
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            evaluate()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        out[name] = {"ms_per_evaluation": ms, "value": w.M * w.ns / (ms * 1e-3),
+                     "schedule": {0: "axis", 1: "fused", 2: "fused"}[ctx.pft_fused_planes()]}
+        ctx.close()
+    return out
+
+
 def batched_gain(binding, inputs, count: int, steps: int):
     """Uneven replicas (grids 24-48^3, Ns 40-80): complex64 propagators, all
     replicas per launch, field steps replayed from a HIP graph -- against the
@@ -230,6 +265,7 @@ def main():
     ap.add_argument("--batch-replicas", type=int, default=256,
                     help="replicas in the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-edwards", action="store_true", help="skip the Edwards-model timing")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the library's plain copy kernel on this many MiB (counter scale)")
     args = ap.parse_args()
@@ -285,6 +321,11 @@ def main():
         res[precision] = run_precision(binding, w, wp, wm, precision, args.steps, args.warmup, scheme)
         log(f"[bench] {precision}: {res[precision]['ms_per_step']:.3f} ms/eval, "
             f"{res[precision]['value']:.3e} site-steps/s, roofline {res[precision]['roofline']}")
+    edwards = None
+    if not args.no_edwards:
+        log("[bench] Edwards homopolymer model, 128^3, Ns = 100")
+        edwards = edwards_run(binding, inputs, args.steps, args.warmup)
+        log(f"[bench] edwards: {edwards}")
     batched = None
     if args.batch_replicas > 0:
         log(f"[bench] batched replicas: {args.batch_replicas}, {args.batch_steps} field steps")
@@ -323,6 +364,8 @@ def main():
         line["kernel_variants"] = tuned
     if batched is not None:
         line["batched"] = batched
+    if edwards is not None:
+        line["edwards"] = edwards
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],

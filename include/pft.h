@@ -70,7 +70,21 @@ typedef struct {
     double C;           /* chain number density parameter, > 0 (Eq. (3))      */
     int32_t precision;  /* pft_precision                                      */
     int32_t scheme;     /* pft_scheme                                         */
+    int32_t model;      /* pft_model (0 = the AB diblock melt of Eq. (3))     */
+    double B;           /* Edwards model: excluded-volume parameter, > 0       */
 } pft_params;
+
+/* Models.  PFT_DIBLOCK: the incompressible AB diblock melt, Eq. (3), fields
+ * (w_+, w_-).  PFT_EDWARDS: homopolymers in implicit solvent, Eq. (2),
+ *   H[omega] = (B/2) int dx omega^2 - C V ln Q[i omega],
+ * one field omega passed as w_plus (w_minus is ignored and may be NULL); f and
+ * chiN are ignored.  The chain is symmetric, so q-dagger = q: pft_propagate
+ * runs the forward sweep only (half the diblock work) over K = ns equal steps,
+ * pft_densities writes phi to phi_a and zeros to phi_b, and pft_cl_step uses
+ * the force per unit C dV  F = (B/C) omega + i phi  (omega <- omega -
+ * lambda_plus dt F + s xi, noise field 0).  pft_adjoint and batches accept the
+ * diblock model only (PFT_E_UNSUPPORTED). */
+typedef enum { PFT_DIBLOCK = 0, PFT_EDWARDS = 1 } pft_model;
 
 /* One explicit Euler-Maruyama step of the field equation of motion, Eq. (9):
  *   w_+ <- w_+ - lambda_+ dt F_+ + s_+ xi_+,  w_- <- w_- - lambda_- dt F_- + s_- xi_-,

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libpft.so")
 PFT_OK, PFT_E_INVALID, PFT_E_UNSUPPORTED, PFT_E_NOMEM, PFT_E_DEVICE, PFT_E_NONFINITE, PFT_E_STATE = range(7)
 PFT_C128, PFT_C64 = 0, 1
 PFT_RQM4, PFT_SPLIT2 = 0, 1
+PFT_DIBLOCK, PFT_EDWARDS = 0, 1
 
 SUPPORTED_AXES = (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 192, 256)
 
@@ -55,7 +56,8 @@ class pft_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("ns", ctypes.c_int32), ("f", ctypes.c_double), ("chiN", ctypes.c_double),
-                ("C", ctypes.c_double), ("precision", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+                ("C", ctypes.c_double), ("precision", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("B", ctypes.c_double)]
 
 
 class pft_step(ctypes.Structure):
@@ -171,10 +173,12 @@ class Params:
     C: float = 1.0
     precision: int = PFT_C128
     scheme: int = PFT_RQM4
+    model: int = 0
+    B: float = 0.0
 
     def c(self) -> pft_params:
         return pft_params(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.ns, self.f,
-                          self.chiN, self.C, self.precision, self.scheme)
+                          self.chiN, self.C, self.precision, self.scheme, self.model, self.B)
 
 
 class Context:
@@ -210,7 +214,13 @@ class Context:
     # -- entry points -------------------------------------------------------
     def pft_propagate(self, w_plus, w_minus):
         self._check(load().pft_propagate(self._h, _field(w_plus, self.shape, "w_plus"),
-                                         _field(w_minus, self.shape, "w_minus")))
+                                         self._wm(w_minus)))
+
+    def _wm(self, w_minus):
+        # the Edwards model has one field (passed as w_plus); w_minus may be None
+        if w_minus is None and self.params.model == PFT_EDWARDS:
+            return None
+        return _field(w_minus, self.shape, "w_minus")
 
     def pft_densities(self, phi_a, phi_b, Q=None):
         self._check(load().pft_densities(self._h, _field(phi_a, self.shape, "phi_a"),
@@ -218,12 +228,12 @@ class Context:
 
     def pft_hamiltonian(self, w_plus, w_minus, H, h_intensive=None):
         self._check(load().pft_hamiltonian(self._h, _field(w_plus, self.shape, "w_plus"),
-                                           _field(w_minus, self.shape, "w_minus"),
+                                           self._wm(w_minus),
                                            _field(H, (1,), "H"), _opt(h_intensive, (1,), "h")))
 
     def pft_cl_step(self, w_plus, w_minus, step: pft_step, phi_a=None, phi_b=None, Q=None, H=None):
         self._check(load().pft_cl_step(self._h, _field(w_plus, self.shape, "w_plus"),
-                                       _field(w_minus, self.shape, "w_minus"), ctypes.byref(step),
+                                       self._wm(w_minus), ctypes.byref(step),
                                        _opt(phi_a, self.shape, "phi_a"), _opt(phi_b, self.shape, "phi_b"),
                                        _opt(Q, (1,), "Q"), _opt(H, (1,), "H")))
 
@@ -286,8 +296,9 @@ class Context:
         return {k: (float(ms[i]), int(cnt[i]), float(by[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     # -- conveniences (allocate outputs, still all-GPU) ----------------------
-    def evaluate(self, w_plus, w_minus):
-        """propagate + densities + hamiltonian; returns dict of GPU tensors."""
+    def evaluate(self, w_plus, w_minus=None):
+        """propagate + densities + hamiltonian; returns dict of GPU tensors
+        (Edwards model: w_plus is omega, w_minus None, phiA is phi)."""
         dev = w_plus.device
         phi_a = torch.empty(self.shape, dtype=torch.complex128, device=dev)
         phi_b = torch.empty_like(phi_a)

@@ -87,8 +87,8 @@ __device__ __forceinline__ void field_tables_body(const double2* __restrict__ wp
                                TabDesc d, cx<T>* __restrict__ out)
 {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
-        const double2 p = wp[x], m = wm[x];
-        // w_A = i w_+ - w_-, w_B = i w_+ + w_-
+        const double2 p = wp[x], m = wm ? wm[x] : make_double2(0.0, 0.0);
+        // w_A = i w_+ - w_-, w_B = i w_+ + w_- (no w_- array: w_- = 0, the Edwards field i omega)
         const double2 wA = make_double2(-p.y - m.x, p.x - m.y);
         const double2 wB = make_double2(-p.y + m.x, p.x + m.y);
         for (int k = 0; k < d.n; ++k) {
@@ -242,7 +242,7 @@ __device__ __forceinline__ void ham_partials_body(const double2* __restrict__ wp
     __shared__ double2 sh[kRedThreads];
     NSum re, im;
     for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < M; i += (int64_t)gridDim.x * kRedThreads) {
-        const double2 m = wm[i], p = wp[i];
+        const double2 m = wm[i], p = wp ? wp[i] : make_double2(0.0, 0.0);
         const double2 m2 = cmul(m, m);
         re.add(m2.x * inv_chiN + p.y);
         im.add(m2.y * inv_chiN - p.x);
@@ -365,6 +365,8 @@ struct UpdArgs {
     double two_over_chiN, dtp, dtm, sp, sm;
     int noise;
     uint64_t seed, rep, step;
+    int edwards;       // Edwards model: wp holds omega, F = b_over_c omega + i phiA, wm untouched
+    double b_over_c;
 };
 
 __device__ __forceinline__ void update_body(UpdArgs a)
@@ -374,11 +376,17 @@ __device__ __forceinline__ void update_body(UpdArgs a)
         double zp[4] = {0, 0, 0, 0}, zm[4] = {0, 0, 0, 0};
         if (a.noise) {
             normals4(g, 0, a.step, a.seed, a.rep, zp);
-            normals4(g, 1, a.step, a.seed, a.rep, zm);
+            if (!a.edwards) normals4(g, 1, a.step, a.seed, a.rep, zm);
         }
         for (int r = 0; r < 4; ++r) {
             const int64_t x = 4 * g + r;
             if (x >= a.M) break;
+            if (a.edwards) {
+                const double2 ph = a.phiA[x], om = a.wp[x];
+                const double2 F = make_double2(a.b_over_c * om.x - ph.y, a.b_over_c * om.y + ph.x);
+                a.wp[x] = make_double2(om.x - a.dtp * F.x + a.sp * zp[r], om.y - a.dtp * F.y);
+                continue;
+            }
             const double2 pa = a.phiA[x], pb = a.phiB[x], p = a.wp[x], m = a.wm[x];
             // F_+ = i (phi - 1)
             const double2 Fp = make_double2(-(pa.y + pb.y), pa.x + pb.x - 1.0);
@@ -792,7 +800,7 @@ struct pft_ctx {
     size_t elem = 0;                  // bytes per propagator value
     // device buffers
     void* qs = nullptr;
-    void* qds = nullptr;
+    void* qds = nullptr;   // the Edwards model's conjugate store is qs itself (symmetric chain)
     void* U = nullptr;
     void* V = nullptr;
     void* U2 = nullptr;    // work pair of the conjugate sweep when it runs on s2
@@ -1113,6 +1121,10 @@ pft_status field_tables_t(pft_ctx* c, const double* wp, const double* wm)
     d.blk[2] = 0; d.a[2] = c->hval[1] / 4;
     d.blk[3] = 1; d.a[3] = c->hval[2] / 4;
     if (c->K == c->p.ns) d.n = 2;  // no junction sub-steps
+    if (c->p.model == PFT_EDWARDS) {
+        d.n = 1;  // one species: E4 = exp(-i omega h/4)
+        wm = nullptr;
+    }
     {
         ProfScope ps(c, PFT_K_TABLES, (32.0 + d.n * (double)c->elem) * (double)c->M, nullptr, true);
         PFT_LAUNCH((k_field_tables<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
@@ -1128,7 +1140,11 @@ pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
 {
     pft_status s = field_tables_t<T>(c, wp, wm);
     if (s) return s;
-    if (c->s2 && !c->dual_off) {
+    if (c->p.model == PFT_EDWARDS) {
+        // symmetric chain: q-dagger = q, one sweep
+        s = sweep<T>(c, false, c->qs);
+        if (s) return s;
+    } else if (c->s2 && !c->dual_off) {
         // the two sweeps are independent: the conjugate one runs on a second
         // stream with its own work pair, so one sweep's memory phases overlap
         // the other's on-chip transform phases
@@ -1163,9 +1179,12 @@ pft_status hamiltonian_launch(pft_ctx* c, const double* wp, const double* wm, do
 {
     const double V = c->p.lx * c->p.ly * c->p.lz;
     ProfScope ps(c, PFT_K_REDUCE, 2.0 * sizeof(double2) * (double)c->M);
+    // diblock: sum w_-^2/chiN - i w_+;  Edwards (omega in wp): sum (B/(2C)) omega^2
+    const bool ed = c->p.model == PFT_EDWARDS;
     hipLaunchKernelGGL(k_ham_partials, dim3(c->nparts), dim3(kRedThreads), 0, c->stream,
-                       reinterpret_cast<const double2*>(wp), reinterpret_cast<const double2*>(wm), c->M,
-                       1.0 / c->p.chiN, c->partials);
+                       ed ? nullptr : reinterpret_cast<const double2*>(wp),
+                       reinterpret_cast<const double2*>(ed ? wp : wm), c->M,
+                       ed ? c->p.B / (2.0 * c->p.C) : 1.0 / c->p.chiN, c->partials);
     hipLaunchKernelGGL(k_ham_final, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, c->nparts, c->p.C,
                        V / (double)c->M, V, c->scal, reinterpret_cast<double2*>(H), reinterpret_cast<double2*>(hint),
                        c->scal + 4);
@@ -1596,6 +1615,7 @@ void free_all(pft_ctx* c)
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     c->s2 = nullptr;
+    if (c->qds == c->qs) c->qds = nullptr;
     void* bufs[] = {c->qs,  c->qds,  c->U,        c->V,    c->U2,    c->V2,  c->E,   c->work,
                     c->gtab, c->tau, c->phi,      c->partials, c->scal, c->flags, c->adj, c->adjG,
                     c->adjAcc};
@@ -2140,10 +2160,13 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
     *out = nullptr;
     if (!params) return PFT_E_INVALID;
     const pft_params& p = *params;
-    if (p.nx < 1 || p.ny < 1 || p.nz < 1 || !(p.lx > 0) || !(p.ly > 0) || !(p.lz > 0) || p.ns < 2 ||
-        !(p.f > 0.0 && p.f < 1.0) || !(p.chiN > 0) || !(p.C > 0) || (p.precision != PFT_C128 && p.precision != PFT_C64) ||
-        (p.scheme != PFT_RQM4 && p.scheme != PFT_SPLIT2))
+    const bool ed = p.model == PFT_EDWARDS;
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1 || !(p.lx > 0) || !(p.ly > 0) || !(p.lz > 0) || p.ns < 2 || !(p.C > 0) ||
+        (p.precision != PFT_C128 && p.precision != PFT_C64) || (p.scheme != PFT_RQM4 && p.scheme != PFT_SPLIT2) ||
+        (p.model != PFT_DIBLOCK && p.model != PFT_EDWARDS))
         return PFT_E_INVALID;
+    if (ed ? !(p.B > 0) : (!(p.f > 0.0 && p.f < 1.0) || !(p.chiN > 0))) return PFT_E_INVALID;
+    if (ed) dual = false;  // one sweep: no conjugate stream
     if (!pft::axis_supported(p.nx) || !pft::axis_supported(p.ny) || !pft::axis_supported(p.nz))
         return PFT_E_UNSUPPORTED;
 
@@ -2164,7 +2187,17 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
     c->elem = p.precision == PFT_C128 ? sizeof(cx<double>) : sizeof(cx<float>);
     c->h.resize(p.ns + 1);
     c->blk.resize(p.ns + 1);
-    c->K = contour_plan(p.ns, p.f, c->h.data(), c->blk.data(), &c->J);
+    if (ed) {
+        // one species along the whole chain: K = ns equal steps, no junction
+        c->K = p.ns;
+        for (int j = 0; j < p.ns; ++j) {
+            c->h[j] = 1.0 / p.ns;
+            c->blk[j] = 0;
+        }
+        c->J = c->K;
+    } else {
+        c->K = contour_plan(p.ns, p.f, c->h.data(), c->blk.data(), &c->J);
+    }
     const double ds = 1.0 / p.ns;
     c->hval[0] = ds;
     c->kind.resize(c->K);
@@ -2191,7 +2224,7 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
 
     auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess; };
     const size_t store = (size_t)(c->K + 1) * c->M * c->elem;
-    bool ok = alloc(&c->qs, store) && alloc(&c->qds, store) && alloc(&c->U, c->M * c->elem) &&
+    bool ok = alloc(&c->qs, store) && (ed || alloc(&c->qds, store)) && alloc(&c->U, c->M * c->elem) &&
               alloc(&c->V, c->M * c->elem) && (!dual || (alloc(&c->U2, c->M * c->elem) && alloc(&c->V2, c->M * c->elem))) &&
               alloc(&c->E, 4 * c->M * c->elem) && alloc(&c->work, 2 * c->M * c->elem) &&
               alloc(&c->gtab, (size_t)5 * 2 * 3 * c->maxN * (c->elem / 2)) &&
@@ -2204,6 +2237,7 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
         delete c;
         return PFT_E_NOMEM;
     }
+    if (ed) c->qds = c->qs;  // symmetric chain: the conjugate propagator is q
     pft_status s = PFT_OK;
     if (dual && (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
                  hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -2242,7 +2276,9 @@ int32_t pft_num_steps(const pft_ctx* c) { return c ? c->K : -1; }
 pft_status pft_propagate(pft_ctx* c, const double* wp, const double* wm)
 {
     if (!c) return PFT_E_INVALID;
-    if (!aligned16(wp) || !aligned16(wm)) return c->fail(PFT_E_INVALID, "w_plus/w_minus must be non-null and 16-byte aligned");
+    const bool need_wm = c->p.model != PFT_EDWARDS;
+    if (!aligned16(wp) || (need_wm && !aligned16(wm)))
+        return c->fail(PFT_E_INVALID, "w_plus/w_minus must be non-null and 16-byte aligned");
     c->propagated = false;
     return c->p.precision == PFT_C128 ? propagate_t<double>(c, wp, wm) : propagate_t<float>(c, wp, wm);
 }
@@ -2259,7 +2295,7 @@ pft_status pft_densities(pft_ctx* c, double* phi_a, double* phi_b, double* Q)
 pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, double* H, double* hint)
 {
     if (!c) return PFT_E_INVALID;
-    if (!aligned16(wp) || !aligned16(wm) || !aligned16(H) || (hint && !aligned16(hint)))
+    if (!aligned16(wp) || (c->p.model != PFT_EDWARDS && !aligned16(wm)) || !aligned16(H) || (hint && !aligned16(hint)))
         return c->fail(PFT_E_INVALID, "w_plus/w_minus/H must be non-null and 16-byte aligned");
     if (!c->propagated) return c->fail(PFT_E_STATE, "pft_hamiltonian needs a prior pft_propagate");
     return hamiltonian_launch(c, wp, wm, H, hint);
@@ -2298,6 +2334,11 @@ pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, d
     a.seed = st->seed;
     a.rep = st->replica;
     a.step = st->step;
+    if (c->p.model == PFT_EDWARDS) {
+        a.edwards = 1;
+        a.b_over_c = c->p.B / c->p.C;
+        a.wm = nullptr;
+    }
     ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
     hipLaunchKernelGGL(k_update, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
     PFT_HIP(c, hipGetLastError());
@@ -2367,6 +2408,7 @@ pft_status pft_adjoint(pft_ctx* c, const double* wp, const double* wm, int32_t c
         (H && !aligned16(H)))
         return c->fail(PFT_E_INVALID, "pft_adjoint: pointers must be non-null (dH_dL, H optional) and 16-byte aligned");
     if (ckpt_every < 0) return c->fail(PFT_E_INVALID, "pft_adjoint: ckpt_every must be >= 0");
+    if (c->p.model != PFT_DIBLOCK) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: diblock model only");
     int Kc = ckpt_every;
     if (Kc == 0) Kc = (int)std::ceil(std::sqrt((double)c->K));
     Kc = std::max(1, std::min(Kc, c->K));
@@ -2424,6 +2466,8 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     if (!params || n < 1) return PFT_E_INVALID;
     for (int r = 1; r < n; ++r)
         if (params[r].precision != params[0].precision || params[r].scheme != params[0].scheme) return PFT_E_INVALID;
+    for (int r = 0; r < n; ++r)
+        if (params[r].model != PFT_DIBLOCK) return PFT_E_UNSUPPORTED;
     pft_batch* b = new (std::nothrow) pft_batch();
     if (!b) return PFT_E_NOMEM;
     b->n = n;

@@ -81,7 +81,13 @@ GRAD96 = Workload("grad96", (96, 96, 96), (5.5,) * 3, 128, 0.3, 18.0, C=1.0, see
 CL256 = Workload("cl256", (256, 256, 256), (16.0,) * 3, 200, 0.35, 22.0, C=100.0, seed=1209,
                  sigma=(0.2, 0.05, 0.2, 0.05), dt=0.005, noise=True, steps=200)
 
-WORKLOADS = {w.name: w for w in (LAM128, GYR128, SCFT16, CL64, GRAD96, CL256)}
+# Edwards homopolymer solution (Eq. (2)) on the benchmark grid: 128^3, the
+# lamellar cell, 100 contour steps, C = 1, excluded volume B = 1; the one field
+# omega is the w+ draw (w- is not used).
+EDW128 = Workload("edw128", (128, 128, 128), (10.89,) * 3, 100, 0.5, 1.0, C=1.0, seed=1210,
+                  sigma=(0.1, 0.02, 0.0, 0.0), extra={"model": "edwards", "B": 1.0})
+
+WORKLOADS = {w.name: w for w in (LAM128, GYR128, SCFT16, CL64, GRAD96, CL256, EDW128)}
 
 
 def batch_replicas(count: int = 256, seed: int = 1208):
