@@ -114,6 +114,9 @@ def lib():
             "or_edwards_force": (None, [P, f64, vp, vp, vp]),
             "or_edwards_em_update": (None, [P, f64, vp, vp, f64, f64, i32, u64, u64, u64]),
             "or_edwards_evaluate": (ctypes.c_int, [P, f64, vp, vp, vp, vp, vp]),
+            "or_debye": (f64, [f64]),
+            "or_sis_update": (None, [P, vp, vp, vp, vp, f64, f64, f64, i32, u64, u64, u64]),
+            "or_edwards_sis_update": (None, [P, f64, vp, vp, f64, f64, i32, u64, u64, u64]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(_lib, name)
@@ -340,3 +343,27 @@ def edwards_evaluate(p: Params, B: float, omega):
     hi = np.zeros(1, np.complex128)
     K = lib().or_edwards_evaluate(ctypes.byref(p._c()), B, _ptr(omega), _ptr(phi), _ptr(Q), _ptr(H), _ptr(hi))
     return {"phi": phi, "Q": complex(Q[0]), "H": complex(H[0]), "h": complex(hi[0]), "K": K}
+
+
+# ------------------------------------------------------ semi-implicit step --
+
+def debye(x: float) -> float:
+    return lib().or_debye(float(x))
+
+
+def sis_update(p: Params, wp, wm, phiA, phiB, dt, lam_p=1.0, lam_m=1.0, noise=False, seed=0, replica=0, step_=0):
+    """Return the updated (w_+, w_-) after one semi-implicit step (Eq. (10))."""
+    wp = np.array(wp, dtype=np.complex128, order="C", copy=True)
+    wm = np.array(wm, dtype=np.complex128, order="C", copy=True)
+    phiA, phiB = _cfield(phiA, p.shape), _cfield(phiB, p.shape)
+    lib().or_sis_update(ctypes.byref(p._c()), _ptr(wp), _ptr(wm), _ptr(phiA), _ptr(phiB),
+                        dt, lam_p, lam_m, int(bool(noise)), seed, replica, step_)
+    return wp, wm
+
+
+def edwards_sis_update(p: Params, B: float, omega, phi, dt, lam=1.0, noise=False, seed=0, replica=0, step_=0):
+    omega = np.array(omega, dtype=np.complex128, order="C", copy=True)
+    phi = _cfield(phi, p.shape)
+    lib().or_edwards_sis_update(ctypes.byref(p._c()), B, _ptr(omega), _ptr(phi), dt, lam, int(bool(noise)),
+                                seed, replica, step_)
+    return omega

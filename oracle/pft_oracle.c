@@ -561,6 +561,85 @@ int or_evaluate(const or_params *p, const cplx *wp, const cplx *wm,
 }
 
 /* ------------------------------------------------------------------------ */
+/* First-order semi-implicit field step (Eq. (10) and the effective step of  */
+/* Eq. (11)).  The linear part L of the force is taken implicitly, mode by   */
+/* mode in reciprocal space:                                                 */
+/*   w^(t+dt)(k) = w^t(k) - [lam dt F^t(k) - eta(k)] / (1 + lam dt g(k)).     */
+/* Readings: the noise is divided by the same factor (solving Eq. (10) for   */
+/* w^(t+dt) gives it so; Eq. (11) writes the transformed noise as one term); */
+/* g is the linear response per unit C dV of the force to its own field:    */
+/*   diblock w_+ : g = g_D(|k|^2), the Debye function of the whole chain     */
+/*                 (delta(phi_A + phi_B) = -g_D delta(i w_+) in the weak-   */
+/*                 field limit), g_D(0) = 1;                                  */
+/*   diblock w_- : g = 2 / chiN, the explicitly linear term of F_- (the      */
+/*                 density part of F_- stays explicit), so this update is    */
+/*                 local in real space;                                      */
+/*   Edwards     : g = B / C + g_D(|k|^2).                                    */
+/* Lengths are in units of R_g, so the Debye argument is |k|^2 R_g^2 = |k|^2. */
+/* ------------------------------------------------------------------------ */
+
+/* Debye function of a whole Gaussian chain, g_D(x) = 2 (e^-x + x - 1) / x^2.
+ * Below x = 0.5 the direct form loses digits to cancellation; there the
+ * series 2 sum_m (-x)^m / (m+2)!, m = 0..20, is used (truncation < 1e-25). */
+double or_debye(double x)
+{
+    if (x < 0.5) {
+        double term = 1.0, sum = 1.0; /* m = 0: 2 / 2! */
+        for (int m = 1; m <= 20; m++) {
+            term *= -x / (double)(m + 2);
+            sum += term;
+        }
+        return sum;
+    }
+    return 2.0 * (exp(-x) + x - 1.0) / (x * x);
+}
+
+/* u <- u - IDFT[ DFT(r) / (1 + a g(k)) ] with g(k) = g0 + gD * g_D(|k|^2). */
+static void sis_apply(const or_params *p, cplx *u, const cplx *r, double a, double g0, double gD)
+{
+    const int64_t M = grid_m(p);
+    cplx *t = (cplx *)malloc(sizeof(cplx) * M);
+    memcpy(t, r, sizeof(cplx) * M);
+    dft3(p, t, -1);
+    for (int64_t jx = 0; jx < p->nx; jx++)
+        for (int64_t jy = 0; jy < p->ny; jy++)
+            for (int64_t jz = 0; jz < p->nz; jz++) {
+                const int64_t x = (jx * p->ny + jy) * p->nz + jz;
+                const double g = g0 + gD * or_debye(ksq(p, jx, jy, jz));
+                t[x] = t[x] / (1.0 + a * g);
+            }
+    dft3(p, t, +1);
+    for (int64_t x = 0; x < M; x++) u[x] -= t[x] / (double)M;
+    free(t);
+}
+
+/* Diblock: both fields at once from the forces of the current fields. */
+void or_sis_update(const or_params *p, cplx *wp, cplx *wm, const cplx *phiA, const cplx *phiB,
+                   double dt, double lam_p, double lam_m, int32_t noise,
+                   uint64_t seed, uint64_t replica, uint64_t step)
+{
+    const int64_t M = grid_m(p);
+    const double dV = p->lx * p->ly * p->lz / (double)M;
+    cplx *Fp = (cplx *)malloc(sizeof(cplx) * M);
+    cplx *Fm = (cplx *)malloc(sizeof(cplx) * M);
+    double *xp = (double *)calloc(M, sizeof(double));
+    double *xm = (double *)calloc(M, sizeof(double));
+    or_forces(p, wm, phiA, phiB, Fp, Fm);
+    if (noise) {
+        or_gaussian(seed, replica, step, 0, M, xp);
+        or_gaussian(seed, replica, step, 1, M, xm);
+    }
+    const double sp = noise ? sqrt(2.0 * lam_p * dt / (p->C * dV)) : 0.0;
+    const double sm = noise ? sqrt(2.0 * lam_m * dt / (p->C * dV)) : 0.0;
+    /* r = lam dt F - s xi, the explicit increment with its sign flipped */
+    for (int64_t x = 0; x < M; x++) Fp[x] = lam_p * dt * Fp[x] - sp * xp[x];
+    sis_apply(p, wp, Fp, lam_p * dt, 0.0, 1.0);
+    const double den = 1.0 + lam_m * dt * 2.0 / p->chiN;
+    for (int64_t x = 0; x < M; x++) wm[x] -= (lam_m * dt * Fm[x] - sm * xm[x]) / den;
+    free(Fp); free(Fm); free(xp); free(xm);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Edwards model of homopolymers in an implicit solvent, Eq. (2):           */
 /*   H[omega] = (B/2) int dx omega^2 - C V ln Q[i omega].                     */
 /* One chain species feels w = i omega along the whole contour; the chain is */
@@ -644,6 +723,22 @@ void or_edwards_em_update(const or_params *p, double B, cplx *omega, const cplx 
     if (noise) or_gaussian(seed, replica, step, 0, M, xi);
     const double sg = noise ? sqrt(2.0 * lam * dt / (p->C * dV)) : 0.0;
     for (int64_t x = 0; x < M; x++) omega[x] = omega[x] - lam * dt * F[x] + sg * xi[x];
+    free(F); free(xi);
+}
+
+/* Semi-implicit step for omega with g = B/C + g_D(|k|^2) (see or_sis_update). */
+void or_edwards_sis_update(const or_params *p, double B, cplx *omega, const cplx *phi, double dt, double lam,
+                           int32_t noise, uint64_t seed, uint64_t replica, uint64_t step)
+{
+    const int64_t M = grid_m(p);
+    const double dV = p->lx * p->ly * p->lz / (double)M;
+    cplx *F = (cplx *)malloc(sizeof(cplx) * M);
+    double *xi = (double *)calloc(M, sizeof(double));
+    or_edwards_force(p, B, omega, phi, F);
+    if (noise) or_gaussian(seed, replica, step, 0, M, xi);
+    const double sg = noise ? sqrt(2.0 * lam * dt / (p->C * dV)) : 0.0;
+    for (int64_t x = 0; x < M; x++) F[x] = lam * dt * F[x] - sg * xi[x];
+    sis_apply(p, omega, F, lam * dt, B / p->C, 1.0);
     free(F); free(xi);
 }
 
