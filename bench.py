@@ -140,6 +140,31 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     return out
 
 
+def update_cost(binding, w, wp0, wm0, steps: int):
+    """Field steps (pft_cl_step: evaluation + update) at the workload, FP64,
+    with the explicit and the semi-implicit update (Eqs. (10)-(11))."""
+    import torch
+    ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, binding.PFT_C128, binding.PFT_RQM4))
+    out = {}
+    for name, upd in (("explicit", 0), ("semi_implicit", 1)):
+        wp, wm = wp0.clone(), wm0.clone()
+        st = binding.pft_step(0.01, 1.0, 1.0, 1204, 0, 0, 1, upd)
+        ctx.pft_cl_step(wp, wm, st)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for k in range(steps):
+            st = binding.pft_step(0.01, 1.0, 1.0, 1204, 0, 1 + k, 1, upd)
+            ctx.pft_cl_step(wp, wm, st)
+        t1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms_per_field_step"] = t0.elapsed_time(t1) / steps
+    out["semi_implicit_extra_ms"] = out["semi_implicit_ms_per_field_step"] - out["explicit_ms_per_field_step"]
+    ctx.close()
+    return out
+
+
 def edwards_run(binding, inputs, steps: int, warmup: int):
     """Edwards homopolymer model at 128^3, Ns = 100: one forward sweep per
     evaluation (q-dagger = q), in both working precisions."""
@@ -321,6 +346,11 @@ def main():
         res[precision] = run_precision(binding, w, wp, wm, precision, args.steps, args.warmup, scheme)
         log(f"[bench] {precision}: {res[precision]['ms_per_step']:.3f} ms/eval, "
             f"{res[precision]['value']:.3e} site-steps/s, roofline {res[precision]['roofline']}")
+    upd = None
+    if not args.no_edwards:
+        log("[bench] field step cost: explicit vs semi-implicit update (FP64)")
+        upd = update_cost(binding, w, wp, wm, max(2, args.steps // 4))
+        log(f"[bench] field update: {upd}")
     edwards = None
     if not args.no_edwards:
         log("[bench] Edwards homopolymer model, 128^3, Ns = 100")
@@ -366,6 +396,8 @@ def main():
         line["batched"] = batched
     if edwards is not None:
         line["edwards"] = edwards
+    if upd is not None:
+        line["field_update"] = upd
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],

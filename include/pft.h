@@ -96,6 +96,14 @@ typedef struct {
     double dt, lambda_plus, lambda_minus;
     uint64_t seed, replica, step;
     int32_t noise;
+    int32_t update;  /* 0: the explicit step above; 1: first-order semi-implicit,
+                        Eqs. (10)-(11): every Fourier mode of the increment
+                        lambda dt F - s xi is divided by 1 + lambda dt g(k), with
+                        g = g_D(|k|^2) (Debye function of the whole chain,
+                        lengths in R_g) for w_+, g = 2/chiN for w_- (its
+                        explicitly linear term; local in real space), and
+                        g = B/C + g_D(|k|^2) for the Edwards field.  Batches
+                        accept 0 only. */
 } pft_step;
 
 /* Create a context for one parameter set on the current HIP device.

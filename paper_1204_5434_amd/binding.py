@@ -63,7 +63,8 @@ class pft_params(ctypes.Structure):
 class pft_step(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("lambda_plus", ctypes.c_double),
                 ("lambda_minus", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("replica", ctypes.c_uint64), ("step", ctypes.c_uint64), ("noise", ctypes.c_int32)]
+                ("replica", ctypes.c_uint64), ("step", ctypes.c_uint64), ("noise", ctypes.c_int32),
+                ("update", ctypes.c_int32)]
 
 
 _lib = None

@@ -327,9 +327,8 @@ __device__ __forceinline__ void dft(cx<T>* v)
 // lay(k1, n2) maps an element of the exchanged N1 x N2 matrix of this lane's
 // line to its LDS slot.  Every lane of the workgroup must call diffuse()
 // (it contains barriers); lanes without a line pass zeros.
-template <int N1, int N2, typename T, class Lay>
-__device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay,
-                                        const T* __restrict__ g)
+template <int N1, int N2, typename T, class Lay, class G>
+__device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay, const G& g)
 {
     constexpr int N = N1 * N2;
     if constexpr (N2 == 1) {
@@ -361,6 +360,62 @@ __device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict
                 const T gk = g[k1 + N1 * k2];
                 b[k2] = gk * b[k2];
             });
+            dft<N2, true>(b);
+            sfor<0, N2>([&](auto M2) { sh[lay(k1, decltype(M2)::value)] = b[decltype(M2)::value]; });
+        });
+        __syncthreads();
+        sfor<0, N1>([&](auto K1) { a[decltype(K1)::value] = sh[lay(decltype(K1)::value, t)]; });
+        twiddle<N1, N, true>(a, t);
+        dft<N1, true>(a);
+    }
+}
+
+// ------------------------------------------- one-way line transforms ------
+// line_forward: the line held as in diffuse() (lane t owns n = n1 N2 + t) is
+// replaced by its unnormalised DFT, handed out in natural order: store(k, X[k])
+// is called once for every k the lane ends up owning.  line_inverse is the
+// reverse: load(k) supplies X[k] in natural order and the lane receives its
+// points of the unnormalised inverse DFT in a[].  Both contain barriers.
+template <int N1, int N2, typename T, class Lay, class Store>
+__device__ __forceinline__ void line_forward(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay,
+                                             const Store& store)
+{
+    constexpr int N = N1 * N2;
+    if constexpr (N2 == 1) {
+        dft<N1, false>(a);
+        sfor<0, N1>([&](auto K) { store(decltype(K)::value, a[decltype(K)::value]); });
+    } else {
+        constexpr int NB = N1 / N2;
+        dft<N1, false>(a);
+        twiddle<N1, N, false>(a, t);
+        __syncthreads();
+        sfor<0, N1>([&](auto K1) { sh[lay(decltype(K1)::value, t)] = a[decltype(K1)::value]; });
+        __syncthreads();
+        sfor<0, NB>([&](auto I) {
+            const int k1 = t + N2 * decltype(I)::value;
+            cx<T> b[N2];
+            sfor<0, N2>([&](auto M2) { b[decltype(M2)::value] = sh[lay(k1, decltype(M2)::value)]; });
+            dft<N2, false>(b);
+            sfor<0, N2>([&](auto K2) { store(k1 + N1 * decltype(K2)::value, b[decltype(K2)::value]); });
+        });
+    }
+}
+
+template <int N1, int N2, typename T, class Lay, class Load>
+__device__ __forceinline__ void line_inverse(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay,
+                                             const Load& load)
+{
+    constexpr int N = N1 * N2;
+    if constexpr (N2 == 1) {
+        sfor<0, N1>([&](auto K) { a[decltype(K)::value] = load(decltype(K)::value); });
+        dft<N1, true>(a);
+    } else {
+        constexpr int NB = N1 / N2;
+        __syncthreads();
+        sfor<0, NB>([&](auto I) {
+            const int k1 = t + N2 * decltype(I)::value;
+            cx<T> b[N2];
+            sfor<0, N2>([&](auto K2) { b[decltype(K2)::value] = load(k1 + N1 * decltype(K2)::value); });
             dft<N2, true>(b);
             sfor<0, N2>([&](auto M2) { sh[lay(k1, decltype(M2)::value)] = b[decltype(M2)::value]; });
         });

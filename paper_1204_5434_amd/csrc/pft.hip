@@ -17,6 +17,7 @@
 #include "../../include/pft.h"
 #include "kernels.h"
 #include "planes.h"
+#include "sis.h"
 
 using pft::cx;
 
@@ -400,6 +401,51 @@ __device__ __forceinline__ void update_body(UpdArgs a)
 __global__ void k_update(UpdArgs a)
 {
     update_body(a);
+}
+
+// Semi-implicit step, local part: the explicit increment r = lam dt F - s xi of
+// the field filtered in reciprocal space (w_+, or the Edwards omega) goes to R;
+// the diblock's w_- is updated here, its implicit linear term 2/chiN making
+// the filter a constant: w_- <- w_- - (lam dt F_- - s xi) / (1 + 2 lam dt / chiN).
+struct SisIncArgs {
+    const double2* wp;
+    double2* wm;
+    const double2* phiA;
+    const double2* phiB;
+    double2* R;
+    int64_t M;
+    double two_over_chiN, ap, am, sp, sm, den_m;
+    int noise;
+    uint64_t seed, rep, step;
+    int edwards;
+    double b_over_c;
+};
+
+__global__ void k_sis_increment(SisIncArgs a)
+{
+    const int64_t ng = (a.M + 3) / 4;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (int64_t)gridDim.x * blockDim.x) {
+        double zp[4] = {0, 0, 0, 0}, zm[4] = {0, 0, 0, 0};
+        if (a.noise) {
+            normals4(g, 0, a.step, a.seed, a.rep, zp);
+            if (!a.edwards) normals4(g, 1, a.step, a.seed, a.rep, zm);
+        }
+        for (int r = 0; r < 4; ++r) {
+            const int64_t x = 4 * g + r;
+            if (x >= a.M) break;
+            const double2 pa = a.phiA[x], p = a.wp[x];
+            if (a.edwards) {
+                const double2 F = make_double2(a.b_over_c * p.x - pa.y, a.b_over_c * p.y + pa.x);
+                a.R[x] = make_double2(a.ap * F.x - a.sp * zp[r], a.ap * F.y);
+                continue;
+            }
+            const double2 pb = a.phiB[x], m = a.wm[x];
+            const double2 Fp = make_double2(-(pa.y + pb.y), pa.x + pb.x - 1.0);
+            const double2 Fm = make_double2(a.two_over_chiN * m.x + pb.x - pa.x, a.two_over_chiN * m.y + pb.y - pa.y);
+            a.R[x] = make_double2(a.ap * Fp.x - a.sp * zp[r], a.ap * Fp.y);
+            a.wm[x] = make_double2(m.x - (a.am * Fm.x - a.sm * zm[r]) / a.den_m, m.y - a.am * Fm.y / a.den_m);
+        }
+    }
 }
 
 // ------------------------------------------------------------ reverse mode --
@@ -813,6 +859,8 @@ struct pft_ctx {
     void* gtab = nullptr;  // diffusion factors: [hid 3][half/full 2][axis 3][maxN]
     double* tau = nullptr; // 2 (K+1) trapezoid weights
     double2* phi = nullptr;       // internal phi_A, phi_B (2 M)
+    double* k2 = nullptr;         // semi-implicit step: (2 pi m / L)^2 per axis [3][maxN], natural order
+    double2* sisbuf = nullptr;    // semi-implicit step: the filtered increment (M)
     double2* partials = nullptr;  // reduction scratch
     double2* scal = nullptr;      // [0] Q, [1] H, [2] h, [3..] node Q
     uint32_t* flags = nullptr;
@@ -1618,7 +1666,7 @@ void free_all(pft_ctx* c)
     if (c->qds == c->qs) c->qds = nullptr;
     void* bufs[] = {c->qs,  c->qds,  c->U,        c->V,    c->U2,    c->V2,  c->E,   c->work,
                     c->gtab, c->tau, c->phi,      c->partials, c->scal, c->flags, c->adj, c->adjG,
-                    c->adjAcc};
+                    c->adjAcc, c->k2, c->sisbuf};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -2301,6 +2349,78 @@ pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, doubl
     return hamiltonian_launch(c, wp, wm, H, hint);
 }
 
+// Semi-implicit step (Eqs. (10)-(11)) from the explicit step's arguments: the
+// local increment kernel, then the reciprocal-space filter of the w_+ (or
+// omega) increment in five axis passes over a work array.
+static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
+{
+    const pft_params& p = c->p;
+    if (!c->sisbuf) {
+        if (hipMalloc((void**)&c->sisbuf, (size_t)c->M * sizeof(double2)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->sisbuf = nullptr;
+            return c->fail(PFT_E_NOMEM, "semi-implicit step: cannot allocate the work array");
+        }
+    }
+    if (!c->k2) {
+        std::vector<double> k2(3 * (size_t)c->maxN, 0.0);
+        const int n[3] = {p.nx, p.ny, p.nz};
+        const double L[3] = {p.lx, p.ly, p.lz};
+        for (int ax = 0; ax < 3; ++ax)
+            for (int j = 0; j < n[ax]; ++j) {
+                const int m = (j <= n[ax] / 2) ? j : j - n[ax];
+                const double k = kTwoPi * m / L[ax];
+                k2[(size_t)ax * c->maxN + j] = k * k;
+            }
+        if (hipMalloc((void**)&c->k2, k2.size() * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->k2 = nullptr;
+            return c->fail(PFT_E_NOMEM, "semi-implicit step: cannot allocate the k tables");
+        }
+        PFT_HIP(c, hipMemcpy(c->k2, k2.data(), k2.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    SisIncArgs a{};
+    a.wp = u.wp;
+    a.wm = u.wm;
+    a.phiA = u.phiA;
+    a.phiB = u.phiB;
+    a.R = c->sisbuf;
+    a.M = c->M;
+    a.two_over_chiN = u.two_over_chiN;
+    a.ap = u.dtp;
+    a.am = u.dtm;
+    a.sp = u.sp;
+    a.sm = u.sm;
+    a.den_m = 1.0 + u.dtm * u.two_over_chiN;
+    a.noise = u.noise;
+    a.seed = u.seed;
+    a.rep = u.rep;
+    a.step = u.step;
+    a.edwards = u.edwards;
+    a.b_over_c = u.b_over_c;
+    {
+        ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
+        hipLaunchKernelGGL(k_sis_increment, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
+    }
+    PFT_HIP(c, hipGetLastError());
+    pft::SisArgs f{};
+    f.X = reinterpret_cast<cx<double>*>(c->sisbuf);
+    f.W = reinterpret_cast<cx<double>*>(u.wp);
+    f.k2x = c->k2;
+    f.k2y = c->k2 + c->maxN;
+    f.k2z = c->k2 + 2 * (size_t)c->maxN;
+    f.nz = p.nz;
+    f.a = u.dtp;
+    f.g0 = u.edwards ? u.b_over_c : 0.0;
+    f.gD = 1.0;
+    f.inv_M = 1.0 / (double)c->M;
+    for (int kind = 0; kind < 5; ++kind) {
+        ProfScope ps(c, PFT_K_REDUCE, (kind == 4 ? 3.0 : 2.0) * sizeof(double2) * (double)c->M);
+        PFT_HIP(c, pft::launch_sis_pass(kind, p.nx, p.ny, p.nz, f, c->stream));
+    }
+    return PFT_OK;
+}
+
 pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, double* phi_a, double* phi_b,
                        double* Q, double* H)
 {
@@ -2308,6 +2428,7 @@ pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, d
     if (!st) return c->fail(PFT_E_INVALID, "step parameters are NULL");
     if (!(st->dt >= 0) || !(st->lambda_plus >= 0) || !(st->lambda_minus >= 0))
         return c->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
+    if (st->update != 0 && st->update != 1) return c->fail(PFT_E_INVALID, "update must be 0 or 1");
     if ((phi_a && !aligned16(phi_a)) || (phi_b && !aligned16(phi_b)) || (Q && !aligned16(Q)) || (H && !aligned16(H)))
         return c->fail(PFT_E_INVALID, "optional outputs must be 16-byte aligned");
     double* pa = phi_a ? phi_a : reinterpret_cast<double*>(c->phi);
@@ -2339,6 +2460,7 @@ pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, d
         a.b_over_c = c->p.B / c->p.C;
         a.wm = nullptr;
     }
+    if (st->update == 1) return sis_step(c, a);
     ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
     hipLaunchKernelGGL(k_update, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
     PFT_HIP(c, hipGetLastError());
@@ -2575,6 +2697,7 @@ pft_status pft_batch_cl_steps(pft_batch* b, double* const* w_plus, double* const
         return b->fail(PFT_E_INVALID, "pft_batch_cl_steps: bad arguments");
     if (!(step->dt >= 0) || !(step->lambda_plus >= 0) || !(step->lambda_minus >= 0))
         return b->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
+    if (step->update != 0) return b->fail(PFT_E_UNSUPPORTED, "batches take the explicit step only");
     const double* const* wp = const_cast<const double* const*>(w_plus);
     const double* const* wm = const_cast<const double* const*>(w_minus);
     return b->precision == PFT_C128 ? batch_steps_t<double>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0)
