@@ -165,6 +165,43 @@ def update_cost(binding, w, wp0, wm0, steps: int):
     return out
 
 
+def storage_run(binding, w, wp, wm, steps: int, warmup: int):
+    """The benchmark evaluation with the stored-product storage modes: q only
+    in device memory (contour sums during the conjugate sweep), and q staged
+    through pinned host memory."""
+    import torch
+    out = {}
+    for pname, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+        for sname, st in (("q_only", binding.PFT_STORE_Q), ("host", binding.PFT_STORE_HOST)):
+            torch.cuda.synchronize()
+            free0 = torch.cuda.mem_get_info()[0]
+            ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4,
+                                                 binding.PFT_DIBLOCK, 0.0, st))
+            dev_bytes = free0 - torch.cuda.mem_get_info()[0]
+            pa = torch.empty(w.n, dtype=torch.complex128, device="cuda")
+            pb = torch.empty_like(pa)
+
+            def evaluate():
+                ctx.pft_propagate(wp, wm)
+                ctx.pft_densities(pa, pb)
+
+            for _ in range(warmup):
+                evaluate()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                evaluate()
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            out[f"{pname}_{sname}"] = {"ms_per_step": ms, "value": 2.0 * w.M * w.ns / (ms * 1e-3),
+                                       "device_GB": round(dev_bytes / 1e9, 3)}
+            ctx.close()
+    return out
+
+
 def edwards_run(binding, inputs, steps: int, warmup: int):
     """Edwards homopolymer model at 128^3, Ns = 100: one forward sweep per
     evaluation (q-dagger = q), in both working precisions."""
@@ -290,7 +327,8 @@ def main():
     ap.add_argument("--batch-replicas", type=int, default=256,
                     help="replicas in the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--no-edwards", action="store_true", help="skip the Edwards-model timing")
+    ap.add_argument("--no-edwards", action="store_true",
+                    help="skip the Edwards-model, field-update and storage-mode timings")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the library's plain copy kernel on this many MiB (counter scale)")
     args = ap.parse_args()
@@ -346,6 +384,11 @@ def main():
         res[precision] = run_precision(binding, w, wp, wm, precision, args.steps, args.warmup, scheme)
         log(f"[bench] {precision}: {res[precision]['ms_per_step']:.3f} ms/eval, "
             f"{res[precision]['value']:.3e} site-steps/s, roofline {res[precision]['roofline']}")
+    storage = None
+    if not args.no_edwards:
+        log("[bench] storage modes: q only in HBM, q staged in host memory")
+        storage = storage_run(binding, w, wp, wm, max(2, args.steps // 4), 1)
+        log(f"[bench] storage: {storage}")
     upd = None
     if not args.no_edwards:
         log("[bench] field step cost: explicit vs semi-implicit update (FP64)")
@@ -398,6 +441,8 @@ def main():
         line["edwards"] = edwards
     if upd is not None:
         line["field_update"] = upd
+    if storage is not None:
+        line["storage_modes"] = storage
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],

@@ -72,7 +72,23 @@ typedef struct {
     int32_t scheme;     /* pft_scheme                                         */
     int32_t model;      /* pft_model (0 = the AB diblock melt of Eq. (3))     */
     double B;           /* Edwards model: excluded-volume parameter, > 0       */
+    int32_t storage;    /* pft_storage (0 = both propagators in device memory) */
 } pft_params;
+
+/* Where the propagators live (diblock model).
+ * PFT_STORE_BOTH: q and q-dagger, (K+1) slices each, in device memory (needed
+ *   by pft_node_q, pft_get_slice of q-dagger, pft_adjoint; the default).
+ * PFT_STORE_Q: q only in device memory; the conjugate sweep runs after the
+ *   forward one and accumulates tau_j q_j q-dagger_{K-j} into FP64 density
+ *   accumulators as it goes (the stored-product scheme of Sec. IV.C), halving
+ *   the slice memory.
+ * PFT_STORE_HOST: q is staged into pinned host memory during the forward sweep
+ *   (device-to-host copies on a second stream overlapping the passes) and
+ *   fetched back ahead of use during the conjugate sweep (Sec. V's host-memory
+ *   option): device memory is O(M), the host holds (K+1) slices.
+ * With PFT_STORE_Q / PFT_STORE_HOST, pft_node_q, pft_get_slice(which = 1) and
+ * pft_adjoint return PFT_E_UNSUPPORTED, and the sweeps run one after the other. */
+typedef enum { PFT_STORE_BOTH = 0, PFT_STORE_Q = 1, PFT_STORE_HOST = 2 } pft_storage;
 
 /* Models.  PFT_DIBLOCK: the incompressible AB diblock melt, Eq. (3), fields
  * (w_+, w_-).  PFT_EDWARDS: homopolymers in implicit solvent, Eq. (2),

@@ -235,6 +235,40 @@ __global__ void k_density(const cx<T>* __restrict__ qs, const cx<T>* __restrict_
     density_body<T>(qs, qds, K, J, M, tau, Qp, phiA, phiB, Qout);
 }
 
+// Contour sum on the fly (stored-product storage modes): node pair (j, K-j)
+// adds tau^A_j q_j qd_{K-j} and tau^B_j q_j qd_{K-j} to FP64 accumulators
+// (first: overwrite).
+template <typename T>
+__global__ void k_accum_node(const cx<T>* __restrict__ q, const cx<T>* __restrict__ qd, int64_t M, double ta,
+                             double tb, double2* __restrict__ accA, double2* __restrict__ accB, int first)
+{
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
+        const cx<T> a = q[x], b = qd[x];
+        const double2 p = cmul(make_double2(a.re, a.im), make_double2(b.re, b.im));
+        double2 A = make_double2(ta * p.x, ta * p.y), Bv = make_double2(tb * p.x, tb * p.y);
+        if (!first) {
+            const double2 a0 = accA[x], b0 = accB[x];
+            A = make_double2(a0.x + A.x, a0.y + A.y);
+            Bv = make_double2(b0.x + Bv.x, b0.y + Bv.y);
+        }
+        accA[x] = A;
+        accB[x] = Bv;
+    }
+}
+
+// phi = accumulated contour sum / Q.
+__global__ void k_norm_density(const double2* __restrict__ accA, const double2* __restrict__ accB, int64_t M,
+                               const double2* __restrict__ Qp, double2* __restrict__ phiA, double2* __restrict__ phiB,
+                               double2* __restrict__ Qout)
+{
+    const double2 Q = *Qp;
+    if (Qout && blockIdx.x == 0 && threadIdx.x == 0) *Qout = Q;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
+        phiA[x] = cdiv(accA[x], Q);
+        phiB[x] = cdiv(accB[x], Q);
+    }
+}
+
 // Partial sums of w_-^2 / chiN - i w_+ (the local part of Eq. (3)).
 __device__ __forceinline__ void ham_partials_body(const double2* __restrict__ wp,
                                                               const double2* __restrict__ wm, int64_t M,
@@ -830,6 +864,8 @@ int tuned_variant(int prec, int n, int kind)
 }
 }  // namespace
 
+constexpr int kRing = 4;  // device slots per direction of host staging
+
 struct pft_ctx {
     pft_params p{};
     hipStream_t stream = nullptr;
@@ -860,6 +896,12 @@ struct pft_ctx {
     double* tau = nullptr; // 2 (K+1) trapezoid weights
     double2* phi = nullptr;       // internal phi_A, phi_B (2 M)
     double* k2 = nullptr;         // semi-implicit step: (2 pi m / L)^2 per axis [3][maxN], natural order
+    // stored-product storage modes
+    std::vector<double> tau_h;    // host copy of the trapezoid weights
+    void* qh = nullptr;           // PFT_STORE_HOST: pinned host store of q, (K+1) slices
+    void* ring = nullptr;         // device slots: [kRing] staging q, [kRing] prefetched q, [2] q-dagger
+    hipStream_t cs = nullptr;     // copy stream
+    hipEvent_t ev_st[kRing] = {}, ev_cp[kRing] = {}, ev_rd[kRing] = {}, ev_fr[kRing] = {}, ev_done = nullptr;
     double2* sisbuf = nullptr;    // semi-implicit step: the filtered increment (M)
     double2* partials = nullptr;  // reduction scratch
     double2* scal = nullptr;      // [0] Q, [1] H, [2] h, [3..] node Q
@@ -1128,35 +1170,42 @@ pft_status step_body(pft_ctx* c, int j, const Work& w = Work(), cx<T>* capA = nu
     return spass<T>(c, 0, none, {gptr<T>(c, hd, 1, 0), nullptr, nullptr}, w);
 }
 
-// One sweep over the K steps, forward (q) or mirrored (q-dagger), storing
-// every node into `store`.
+// One sweep over the K steps, forward (q) or mirrored (q-dagger).  Node i
+// (i = 0..K, in sweep order) is written to out(i), and after(i) runs once the
+// pass that stores it has been enqueued.
+template <typename T, class Out, class After>
+pft_status sweep_nodes(pft_ctx* c, bool backward, const Work& w, const Out& out, const After& after)
+{
+    auto stepj = [&](int i) { return backward ? c->K - 1 - i : i; };
+    const bool fused = c->fused && (backward || !c->fused_conj_only);
+    pft_status s = fused ? yzpass<T>(c, -1, stepj(0), nullptr, out(0), w) : zpass<T>(c, -1, stepj(0), nullptr, out(0), w);
+    if (s) return s;
+    if ((s = after(0))) return s;
+    for (int i = 0; i < c->K; ++i) {
+        const int j = stepj(i);
+        const int next = i + 1 < c->K ? stepj(i + 1) : -1;
+        if (fused) {
+            // two passes per step: X, then yz completing it and starting the next
+            s = xpass_step<T>(c, j, w);
+            if (s) return s;
+            s = yzpass<T>(c, j, next, nullptr, out(i + 1), w);
+        } else {
+            s = step_body<T>(c, j, w);
+            if (s) return s;
+            s = zpass<T>(c, j, next, nullptr, out(i + 1), w);
+        }
+        if (s) return s;
+        if ((s = after(i + 1))) return s;
+    }
+    return PFT_OK;
+}
+
+// Sweep storing every node into `store`.
 template <typename T>
 pft_status sweep(pft_ctx* c, bool backward, void* store, const Work& w = Work())
 {
-    auto stepj = [&](int i) { return backward ? c->K - 1 - i : i; };
-    if (c->fused && (backward || !c->fused_conj_only)) {
-        // two passes per step: X, then yz completing it and starting the next
-        pft_status s = yzpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0), w);
-        if (s) return s;
-        for (int i = 0; i < c->K; ++i) {
-            const int j = stepj(i);
-            s = xpass_step<T>(c, j, w);
-            if (s) return s;
-            s = yzpass<T>(c, j, i + 1 < c->K ? stepj(i + 1) : -1, nullptr, slice<T>(store, c, i + 1), w);
-            if (s) return s;
-        }
-        return PFT_OK;
-    }
-    pft_status s = zpass<T>(c, -1, stepj(0), nullptr, slice<T>(store, c, 0), w);
-    if (s) return s;
-    for (int i = 0; i < c->K; ++i) {
-        const int j = stepj(i);
-        s = step_body<T>(c, j, w);
-        if (s) return s;
-        s = zpass<T>(c, j, i + 1 < c->K ? stepj(i + 1) : -1, nullptr, slice<T>(store, c, i + 1), w);
-        if (s) return s;
-    }
-    return PFT_OK;
+    return sweep_nodes<T>(c, backward, w, [&](int i) { return slice<T>(store, c, i); },
+                          [](int) { return PFT_OK; });
 }
 
 template <typename T>
@@ -1183,11 +1232,107 @@ pft_status field_tables_t(pft_ctx* c, const double* wp, const double* wm)
     return PFT_OK;
 }
 
+// Q = (1/M) sum_x q_K(x) into scal[0].
+template <typename T>
+pft_status reduce_q(pft_ctx* c, const cx<T>* qK)
+{
+    ProfScope ps(c, PFT_K_REDUCE, (double)c->elem * (double)c->M);
+    hipLaunchKernelGGL((k_sum_partials<T>), dim3(c->nparts), dim3(kRedThreads), 0, c->stream, qK, c->M, c->partials);
+    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kRedThreads), 0, c->stream, c->partials, c->nparts,
+                       1.0 / (double)c->M, c->scal, (double2*)nullptr, c->flags);
+    PFT_HIP(c, hipGetLastError());
+    return PFT_OK;
+}
+
+// Stored-product storage modes: forward sweep into the device store (or
+// staged through device slots into pinned host memory on the copy stream),
+// then the conjugate sweep, whose node i is paired at once with q_{K-i} and
+// added to the FP64 density accumulators (c->phi: A then B).
+template <typename T>
+pft_status propagate_stored_product(pft_ctx* c)
+{
+    const int K = c->K;
+    const int64_t M = c->M;
+    const bool host = c->p.storage == PFT_STORE_HOST;
+    const size_t bytes = (size_t)M * c->elem;
+    cx<T>* ring = static_cast<cx<T>*>(c->ring);
+    auto rs = [&](int k) { return ring + (size_t)k * M; };                            // staging slots
+    auto rp = [&](int k) { return ring + (size_t)(kRing + k) * M; };                  // prefetch slots
+    auto rd = [&](int k) { return ring + (size_t)((host ? 2 * kRing : 0) + k) * M; };  // q-dagger slots
+    char* qh = static_cast<char*>(c->qh);
+    pft_status s;
+    if (!host) {
+        s = sweep<T>(c, false, c->qs);
+    } else {
+        s = sweep_nodes<T>(
+            c, false, Work(),
+            [&](int n) {
+                // the slot's previous node must have reached the host
+                if (n >= kRing) (void)hipStreamWaitEvent(c->stream, c->ev_cp[n % kRing], 0);
+                return rs(n % kRing);
+            },
+            [&](int n) -> pft_status {
+                const int k = n % kRing;
+                PFT_HIP(c, hipEventRecord(c->ev_st[k], c->stream));
+                PFT_HIP(c, hipStreamWaitEvent(c->cs, c->ev_st[k], 0));
+                PFT_HIP(c, hipMemcpyAsync(qh + (size_t)n * bytes, rs(k), bytes, hipMemcpyDeviceToHost, c->cs));
+                PFT_HIP(c, hipEventRecord(c->ev_cp[k], c->cs));
+                return PFT_OK;
+            });
+    }
+    if (s) return s;
+    s = reduce_q<T>(c, host ? rs(K % kRing) : slice<T>(c->qs, c, K));
+    if (s) return s;
+    // q_{K-i} into prefetch slot i % kRing (after its copy to the host: same stream)
+    auto prefetch = [&](int i) -> pft_status {
+        const int k = i % kRing;
+        PFT_HIP(c, hipMemcpyAsync(rp(k), qh + (size_t)(K - i) * bytes, bytes, hipMemcpyHostToDevice, c->cs));
+        PFT_HIP(c, hipEventRecord(c->ev_rd[k], c->cs));
+        return PFT_OK;
+    };
+    if (host)
+        for (int i = 0; i < kRing && i <= K; ++i)
+            if ((s = prefetch(i))) return s;
+    double2* accA = c->phi;
+    double2* accB = c->phi + M;
+    s = sweep_nodes<T>(
+        c, true, Work(), [&](int i) { return rd(i & 1); },
+        [&](int i) -> pft_status {
+            const int j = K - i;
+            const cx<T>* q = host ? rp(i % kRing) : slice<T>(c->qs, c, j);
+            if (host) PFT_HIP(c, hipStreamWaitEvent(c->stream, c->ev_rd[i % kRing], 0));
+            {
+                ProfScope ps(c, PFT_K_DENSITY, (2.0 * c->elem + (i == 0 ? 32.0 : 64.0)) * (double)M);
+                hipLaunchKernelGGL((k_accum_node<T>), dim3(grid_for(M, 256)), dim3(256), 0, c->stream, q, rd(i & 1), M,
+                                   c->tau_h[j], c->tau_h[K + 1 + j], accA, accB, i == 0 ? 1 : 0);
+            }
+            PFT_HIP(c, hipGetLastError());
+            if (host) {
+                PFT_HIP(c, hipEventRecord(c->ev_fr[i % kRing], c->stream));
+                if (i + kRing <= K) {
+                    PFT_HIP(c, hipStreamWaitEvent(c->cs, c->ev_fr[i % kRing], 0));
+                    pft_status e = prefetch(i + kRing);
+                    if (e) return e;
+                }
+            }
+            return PFT_OK;
+        });
+    if (s) return s;
+    if (host) {
+        // later calls on the context stream see every copy finished
+        PFT_HIP(c, hipEventRecord(c->ev_done, c->cs));
+        PFT_HIP(c, hipStreamWaitEvent(c->stream, c->ev_done, 0));
+    }
+    c->propagated = true;
+    return PFT_OK;
+}
+
 template <typename T>
 pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
 {
     pft_status s = field_tables_t<T>(c, wp, wm);
     if (s) return s;
+    if (c->p.storage != PFT_STORE_BOTH) return propagate_stored_product<T>(c);
     if (c->p.model == PFT_EDWARDS) {
         // symmetric chain: q-dagger = q, one sweep
         s = sweep<T>(c, false, c->qs);
@@ -1243,6 +1388,14 @@ pft_status hamiltonian_launch(pft_ctx* c, const double* wp, const double* wm, do
 template <typename T>
 pft_status densities_t(pft_ctx* c, double* phi_a, double* phi_b, double* Q)
 {
+    if (c->p.storage != PFT_STORE_BOTH) {
+        // the contour sums were accumulated during the conjugate sweep
+        hipLaunchKernelGGL(k_norm_density, dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream, c->phi, c->phi + c->M,
+                           c->M, c->scal, reinterpret_cast<double2*>(phi_a), reinterpret_cast<double2*>(phi_b),
+                           reinterpret_cast<double2*>(Q));
+        PFT_HIP(c, hipGetLastError());
+        return PFT_OK;
+    }
     ProfScope ps(c, PFT_K_DENSITY, (2.0 * (c->K + 1) * (double)c->elem + 2.0 * sizeof(double2)) * (double)c->M,
                  nullptr, true);
     PFT_LAUNCH((k_density<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream,
@@ -1269,7 +1422,16 @@ pft_status nodeq_t(pft_ctx* c, double* out)
 template <typename T>
 pft_status get_slice_t(pft_ctx* c, int which, int node, double* out)
 {
-    const cx<T>* src = slice<T>(which ? c->qds : c->qs, c, node);
+    const cx<T>* src;
+    if (c->p.storage == PFT_STORE_HOST) {
+        // bring the host slice into the first staging slot (ordered on the stream)
+        cx<T>* slot = static_cast<cx<T>*>(c->ring);
+        PFT_HIP(c, hipMemcpyAsync(slot, static_cast<const char*>(c->qh) + (size_t)node * c->M * c->elem,
+                                  (size_t)c->M * c->elem, hipMemcpyHostToDevice, c->stream));
+        src = slot;
+    } else {
+        src = slice<T>(which ? c->qds : c->qs, c, node);
+    }
     hipLaunchKernelGGL((k_from_work<T>), dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream, src,
                        reinterpret_cast<double2*>(out), c->M);
     PFT_HIP(c, hipGetLastError());
@@ -1664,9 +1826,24 @@ void free_all(pft_ctx* c)
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     c->s2 = nullptr;
     if (c->qds == c->qs) c->qds = nullptr;
+    if (c->cs) {
+        (void)hipStreamSynchronize(c->cs);
+        (void)hipStreamDestroy(c->cs);
+        c->cs = nullptr;
+    }
+    for (int k = 0; k < kRing; ++k)
+        for (hipEvent_t* e : {&c->ev_st[k], &c->ev_cp[k], &c->ev_rd[k], &c->ev_fr[k]})
+            if (*e) {
+                (void)hipEventDestroy(*e);
+                *e = nullptr;
+            }
+    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
+    c->ev_done = nullptr;
+    if (c->qh) (void)hipHostFree(c->qh);
+    c->qh = nullptr;
     void* bufs[] = {c->qs,  c->qds,  c->U,        c->V,    c->U2,    c->V2,  c->E,   c->work,
                     c->gtab, c->tau, c->phi,      c->partials, c->scal, c->flags, c->adj, c->adjG,
-                    c->adjAcc, c->k2, c->sisbuf};
+                    c->adjAcc, c->k2, c->sisbuf, c->ring};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -2214,7 +2391,9 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
         (p.model != PFT_DIBLOCK && p.model != PFT_EDWARDS))
         return PFT_E_INVALID;
     if (ed ? !(p.B > 0) : (!(p.f > 0.0 && p.f < 1.0) || !(p.chiN > 0))) return PFT_E_INVALID;
-    if (ed) dual = false;  // one sweep: no conjugate stream
+    if (p.storage < PFT_STORE_BOTH || p.storage > PFT_STORE_HOST) return PFT_E_INVALID;
+    if (p.storage != PFT_STORE_BOTH && ed) return PFT_E_UNSUPPORTED;
+    if (ed || p.storage != PFT_STORE_BOTH) dual = false;  // one sweep, or sweeps in sequence
     if (!pft::axis_supported(p.nx) || !pft::axis_supported(p.ny) || !pft::axis_supported(p.nz))
         return PFT_E_UNSUPPORTED;
 
@@ -2272,7 +2451,10 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
 
     auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, std::max<size_t>(bytes, 16)) == hipSuccess; };
     const size_t store = (size_t)(c->K + 1) * c->M * c->elem;
-    bool ok = alloc(&c->qs, store) && (ed || alloc(&c->qds, store)) && alloc(&c->U, c->M * c->elem) &&
+    const bool both = p.storage == PFT_STORE_BOTH, host = p.storage == PFT_STORE_HOST;
+    const size_t slots = host ? 2 * kRing + 2 : (both ? 0 : 2);
+    bool ok = (host || alloc(&c->qs, store)) && (ed || !both || alloc(&c->qds, store)) &&
+              (slots == 0 || alloc(&c->ring, slots * c->M * c->elem)) && alloc(&c->U, c->M * c->elem) &&
               alloc(&c->V, c->M * c->elem) && (!dual || (alloc(&c->U2, c->M * c->elem) && alloc(&c->V2, c->M * c->elem))) &&
               alloc(&c->E, 4 * c->M * c->elem) && alloc(&c->work, 2 * c->M * c->elem) &&
               alloc(&c->gtab, (size_t)5 * 2 * 3 * c->maxN * (c->elem / 2)) &&
@@ -2287,6 +2469,22 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
     }
     if (ed) c->qds = c->qs;  // symmetric chain: the conjugate propagator is q
     pft_status s = PFT_OK;
+    c->tau_h = tau;
+    if (host) {
+        if (hipHostMalloc(&c->qh, store, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            c->qh = nullptr;
+            s = PFT_E_NOMEM;
+        }
+        if (s == PFT_OK && hipStreamCreateWithFlags(&c->cs, hipStreamNonBlocking) != hipSuccess) s = PFT_E_DEVICE;
+        for (int k = 0; k < kRing && s == PFT_OK; ++k)
+            if (hipEventCreateWithFlags(&c->ev_st[k], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_cp[k], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_rd[k], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_fr[k], hipEventDisableTiming) != hipSuccess)
+                s = PFT_E_DEVICE;
+        if (s == PFT_OK && hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) != hipSuccess) s = PFT_E_DEVICE;
+    }
     if (dual && (hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking) != hipSuccess ||
                  hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
                  hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess))
@@ -2472,6 +2670,7 @@ pft_status pft_node_q(pft_ctx* c, double* qnode)
     if (!c) return PFT_E_INVALID;
     if (!aligned16(qnode)) return c->fail(PFT_E_INVALID, "qnode must be non-null and 16-byte aligned");
     if (!c->propagated) return c->fail(PFT_E_STATE, "pft_node_q needs a prior pft_propagate");
+    if (c->p.storage != PFT_STORE_BOTH) return c->fail(PFT_E_UNSUPPORTED, "pft_node_q needs the q-dagger store");
     return c->p.precision == PFT_C128 ? nodeq_t<double>(c, qnode) : nodeq_t<float>(c, qnode);
 }
 
@@ -2481,6 +2680,8 @@ pft_status pft_get_slice(pft_ctx* c, int32_t which, int32_t node, double* out)
     if (!aligned16(out) || (which != 0 && which != 1) || node < 0 || node > c->K)
         return c->fail(PFT_E_INVALID, "bad slice request (which %d, node %d of %d)", which, node, c->K);
     if (!c->propagated) return c->fail(PFT_E_STATE, "pft_get_slice needs a prior pft_propagate");
+    if (which == 1 && c->p.storage != PFT_STORE_BOTH)
+        return c->fail(PFT_E_UNSUPPORTED, "q-dagger slices are not stored in this storage mode");
     return c->p.precision == PFT_C128 ? get_slice_t<double>(c, which, node, out) : get_slice_t<float>(c, which, node, out);
 }
 
@@ -2531,6 +2732,7 @@ pft_status pft_adjoint(pft_ctx* c, const double* wp, const double* wm, int32_t c
         return c->fail(PFT_E_INVALID, "pft_adjoint: pointers must be non-null (dH_dL, H optional) and 16-byte aligned");
     if (ckpt_every < 0) return c->fail(PFT_E_INVALID, "pft_adjoint: ckpt_every must be >= 0");
     if (c->p.model != PFT_DIBLOCK) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: diblock model only");
+    if (c->p.storage != PFT_STORE_BOTH) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: needs both stores");
     int Kc = ckpt_every;
     if (Kc == 0) Kc = (int)std::ceil(std::sqrt((double)c->K));
     Kc = std::max(1, std::min(Kc, c->K));
@@ -2589,7 +2791,7 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     for (int r = 1; r < n; ++r)
         if (params[r].precision != params[0].precision || params[r].scheme != params[0].scheme) return PFT_E_INVALID;
     for (int r = 0; r < n; ++r)
-        if (params[r].model != PFT_DIBLOCK) return PFT_E_UNSUPPORTED;
+        if (params[r].model != PFT_DIBLOCK || params[r].storage != PFT_STORE_BOTH) return PFT_E_UNSUPPORTED;
     pft_batch* b = new (std::nothrow) pft_batch();
     if (!b) return PFT_E_NOMEM;
     b->n = n;
