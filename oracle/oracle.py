@@ -38,7 +38,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("ns", ctypes.c_int32), ("f", ctypes.c_double), ("chiN", ctypes.c_double),
-                ("C", ctypes.c_double), ("scheme", ctypes.c_int32), ("naive_dft", ctypes.c_int32)]
+                ("C", ctypes.c_double), ("scheme", ctypes.c_int32), ("naive_dft", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 3)]
 
 
 @dataclass
@@ -56,6 +57,7 @@ class Params:
     C: float = 1.0
     scheme: int = RQM4
     naive_dft: bool = False
+    bc: tuple = (0, 0, 0)    # per axis: 0 periodic, 1 reflecting (Neumann), 2 absorbing (Dirichlet)
 
     @property
     def shape(self):
@@ -75,7 +77,8 @@ class Params:
         if self.ns < 2:
             raise ValueError("ns must be >= 2")
         return _Params(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.ns,
-                       self.f, self.chiN, self.C, self.scheme, int(self.naive_dft))
+                       self.f, self.chiN, self.C, self.scheme, int(self.naive_dft),
+                       (ctypes.c_int32 * 3)(*self.bc))
 
 
 _lib = None

@@ -46,7 +46,12 @@ typedef struct {
     double C;              /* chain number density parameter (Eq. (3))           */
     int32_t scheme;        /* 0 = Richardson split step (Eq. (12)), 1 = plain split */
     int32_t naive_dft;     /* 1: use the O(M^2) DFT definition, 0: recursive FFT */
+    int32_t bc[3];         /* per axis: 0 periodic (DFT), 1 reflecting walls (Neumann,
+                              cosine transform), 2 absorbing walls (Dirichlet, sine
+                              transform) -- Sec. III, boundary conditions of Eq. (5) */
 } or_params;
+
+enum { OR_PERIODIC = 0, OR_NEUMANN = 1, OR_DIRICHLET = 2 };
 
 enum { OR_RQM4 = 0, OR_SPLIT2 = 1 };
 
@@ -270,11 +275,90 @@ void or_ksq_grid(const or_params *p, double *out)
                 out[(jx * p->ny + jy) * p->nz + jz] = ksq(p, jx, jy, jz);
 }
 
+/*
+ * One-dimensional diffusion exp(h d^2/dx^2) along one axis with walls, exact
+ * on the eigenbasis of the walled Laplacian on the cell-centred grid
+ * x_n = (n + 1/2) L / N:
+ *   reflecting (Neumann): cos(pi m x / L), m = 0..N-1, the DCT-II pair
+ *     X_m = sum_n u_n cos(pi m (n+1/2)/N),
+ *     u_n = X_0 / N + (2/N) sum_{m>=1} X_m cos(pi m (n+1/2)/N);
+ *   absorbing (Dirichlet): sin(pi m x / L), m = 1..N, the DST-II pair
+ *     X_m = sum_n u_n sin(pi m (n+1/2)/N),
+ *     u_n = (2/N) sum_{m<N} X_m sin(pi m (n+1/2)/N) + (1/N) X_N sin(pi N (n+1/2)/N);
+ * each mode decays by exp(-(pi m / L)^2 h).  Written out as the definitions,
+ * O(N^2) per line.
+ */
+static void diffuse_walls_axis(const or_params *p, double h, cplx *u, int axis)
+{
+    const int n = (axis == 0) ? p->nx : (axis == 1) ? p->ny : p->nz;
+    const double L = (axis == 0) ? p->lx : (axis == 1) ? p->ly : p->lz;
+    const ptrdiff_t stride = (axis == 0) ? (ptrdiff_t)p->ny * p->nz : (axis == 1) ? p->nz : 1;
+    const int64_t nlines = grid_m(p) / n;
+    const int dir = p->bc[axis] == OR_DIRICHLET;
+    const double pi = OR_TWO_PI / 2.0;
+    #pragma omp parallel
+    {
+        cplx *in = (cplx *)malloc(sizeof(cplx) * n);
+        cplx *X = (cplx *)malloc(sizeof(cplx) * (n + 1));
+        #pragma omp for schedule(static)
+        for (int64_t l = 0; l < nlines; l++) {
+            ptrdiff_t base;
+            if (axis == 2) base = l * p->nz;
+            else if (axis == 1) base = (l / p->nz) * (ptrdiff_t)p->ny * p->nz + (l % p->nz);
+            else base = l;
+            for (int i = 0; i < n; i++) in[i] = u[base + i * stride];
+            for (int m = dir ? 1 : 0; m <= (dir ? n : n - 1); m++) {
+                cplx acc = 0.0;
+                for (int i = 0; i < n; i++) {
+                    const double arg = pi * m * (i + 0.5) / n;
+                    acc += in[i] * (dir ? sin(arg) : cos(arg));
+                }
+                const double k = pi * m / L;
+                X[m] = acc * exp(-k * k * h);
+            }
+            for (int i = 0; i < n; i++) {
+                cplx acc = 0.0;
+                if (dir) {
+                    for (int m = 1; m < n; m++) acc += 2.0 * X[m] * sin(pi * m * (i + 0.5) / n);
+                    acc += X[n] * sin(pi * n * (i + 0.5) / n);
+                } else {
+                    acc = X[0];
+                    for (int m = 1; m < n; m++) acc += 2.0 * X[m] * cos(pi * m * (i + 0.5) / n);
+                }
+                u[base + i * stride] = acc / (double)n;
+            }
+        }
+        free(in);
+        free(X);
+    }
+}
+
 /* The diffusion operator exp(h Laplacian) of Eq. (5), exact on the Fourier */
-/* basis: u <- IDFT( e^{-|k|^2 h} DFT(u) ) / M.                              */
+/* basis: u <- IDFT( e^{-|k|^2 h} DFT(u) ) / M.  With walls on some axes the */
+/* operator factorises over the axes: the periodic ones diffuse through the  */
+/* 1-D DFT, the walled ones through their sine or cosine basis.              */
 void or_diffuse(const or_params *p, double h, cplx *u)
 {
     const int64_t M = grid_m(p);
+    if (p->bc[0] || p->bc[1] || p->bc[2]) {
+        for (int axis = 0; axis < 3; axis++) {
+            if (p->bc[axis]) {
+                diffuse_walls_axis(p, h, u, axis);
+                continue;
+            }
+            const int n = (axis == 0) ? p->nx : (axis == 1) ? p->ny : p->nz;
+            const double L = (axis == 0) ? p->lx : (axis == 1) ? p->ly : p->lz;
+            fft_axis(u, p->nx, p->ny, p->nz, axis, -1);
+            #pragma omp parallel for schedule(static)
+            for (int64_t x = 0; x < M; x++) {
+                const int64_t j = (axis == 0) ? x / ((int64_t)p->ny * p->nz) : (axis == 1) ? (x / p->nz) % p->ny : x % p->nz;
+                const double k = OR_TWO_PI * or_mode((int32_t)j, n) / L;
+                u[x] *= exp(-k * k * h) / (double)n;
+            }
+            fft_axis(u, p->nx, p->ny, p->nz, axis, +1);
+        }
+        return;
+    }
     dft3(p, u, -1);
     #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < M; k++) {
