@@ -237,6 +237,53 @@ def edwards_run(binding, inputs, steps: int, warmup: int):
     return out
 
 
+def walls_run(binding, w, wp, wm, steps: int, warmup: int):
+    """The benchmark evaluation in walled boxes (Sec. III: cosine modes between
+    reflecting walls, sine modes between absorbing ones): a film with
+    reflecting walls normal to z, and absorbing walls on every axis; both
+    working precisions, with the per-kernel breakdown on one stream."""
+    import torch
+    out = {}
+    for gname, bc in (("film_z_reflecting", (0, 0, 1)), ("box_absorbing", (2, 2, 2))):
+        for pname, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+            ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4,
+                                                 binding.PFT_DIBLOCK, 0.0, binding.PFT_STORE_BOTH, bc))
+            pa = torch.empty(w.n, dtype=torch.complex128, device="cuda")
+            pb = torch.empty_like(pa)
+
+            def evaluate():
+                ctx.pft_propagate(wp, wm)
+                ctx.pft_densities(pa, pb)
+
+            for _ in range(warmup):
+                evaluate()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                evaluate()
+            t1.record()
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / steps
+            ctx.pft_set_concurrent_sweeps(False)
+            ctx.pft_profile_begin()
+            for _ in range(steps):
+                evaluate()
+            prof = ctx.pft_profile_end()
+            if ctx.pft_status_flags():
+                raise RuntimeError("device status flags set in the walled evaluation")
+            kernels = {k: {"ms_per_step": round(v[0] / steps, 4),
+                           "GB_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+                       for k, v in prof.items() if v[1] > 0}
+            out[f"{gname}_{pname}"] = {"bc": list(bc), "ms_per_step": ms,
+                                       "value": 2.0 * w.M * w.ns / (ms * 1e-3),
+                                       "schedule": {0: "axis", 1: "fused", 2: "fused"}[ctx.pft_fused_planes()],
+                                       "kernels": kernels}
+            ctx.close()
+    return out
+
+
 def batched_gain(binding, inputs, count: int, steps: int):
     """Uneven replicas (grids 24-48^3, Ns 40-80): complex64 propagators, all
     replicas per launch, field steps replayed from a HIP graph -- against the
@@ -328,7 +375,7 @@ def main():
                     help="replicas in the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-edwards", action="store_true",
-                    help="skip the Edwards-model, field-update and storage-mode timings")
+                    help="skip the Edwards-model, field-update, storage-mode and walled-box timings")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the library's plain copy kernel on this many MiB (counter scale)")
     args = ap.parse_args()
@@ -394,6 +441,11 @@ def main():
         log("[bench] field step cost: explicit vs semi-implicit update (FP64)")
         upd = update_cost(binding, w, wp, wm, max(2, args.steps // 4))
         log(f"[bench] field update: {upd}")
+    walls = None
+    if not args.no_edwards:
+        log("[bench] walled boxes: reflecting film, absorbing box")
+        walls = walls_run(binding, w, wp, wm, max(2, args.steps // 4), 1)
+        log(f"[bench] walls: {walls}")
     edwards = None
     if not args.no_edwards:
         log("[bench] Edwards homopolymer model, 128^3, Ns = 100")
@@ -443,6 +495,8 @@ def main():
         line["field_update"] = upd
     if storage is not None:
         line["storage_modes"] = storage
+    if walls is not None:
+        line["walls"] = walls
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],

@@ -73,7 +73,21 @@ typedef struct {
     int32_t model;      /* pft_model (0 = the AB diblock melt of Eq. (3))     */
     double B;           /* Edwards model: excluded-volume parameter, > 0       */
     int32_t storage;    /* pft_storage (0 = both propagators in device memory) */
+    int32_t bc[3];      /* per axis x, y, z: pft_boundary (0 = periodic)       */
 } pft_params;
+
+/* Boundary conditions of Eq. (5) per axis (Sec. III: Fourier, cosine and sine
+ * transforms for periodic, Neumann and Dirichlet boundaries).  Walls sit half a
+ * cell outside the grid points x_n = (n + 1/2) L / N.  PFT_REFLECTING: zero
+ * normal derivative (cosine modes, decay exp(-(pi m / L)^2 h), m = 0..N-1);
+ * PFT_ABSORBING: q = 0 on the walls (sine modes, m = 1..N).  A walled axis of
+ * N points runs the periodic kernels of length 2N on the even (reflecting) or
+ * odd (absorbing) mirror image of each line, so N must be one of 8 12 16 20 24
+ * 32 40 48 64 96 128 (else PFT_E_UNSUPPORTED).  Walled contexts run the axis
+ * schedule on walled y or z axes, and pft_adjoint, pft_debug_kgrid, the
+ * semi-implicit step and batches accept periodic boxes only
+ * (PFT_E_UNSUPPORTED). */
+typedef enum { PFT_PERIODIC = 0, PFT_REFLECTING = 1, PFT_ABSORBING = 2 } pft_boundary;
 
 /* Where the propagators live (diblock model).
  * PFT_STORE_BOTH: q and q-dagger, (K+1) slices each, in device memory (needed

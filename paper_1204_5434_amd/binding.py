@@ -24,6 +24,7 @@ PFT_C128, PFT_C64 = 0, 1
 PFT_RQM4, PFT_SPLIT2 = 0, 1
 PFT_DIBLOCK, PFT_EDWARDS = 0, 1
 PFT_STORE_BOTH, PFT_STORE_Q, PFT_STORE_HOST = 0, 1, 2
+PFT_PERIODIC, PFT_REFLECTING, PFT_ABSORBING = 0, 1, 2
 
 SUPPORTED_AXES = (8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 192, 256)
 
@@ -58,7 +59,8 @@ class pft_params(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("ns", ctypes.c_int32), ("f", ctypes.c_double), ("chiN", ctypes.c_double),
                 ("C", ctypes.c_double), ("precision", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("model", ctypes.c_int32), ("B", ctypes.c_double), ("storage", ctypes.c_int32)]
+                ("model", ctypes.c_int32), ("B", ctypes.c_double), ("storage", ctypes.c_int32),
+                ("bc", ctypes.c_int32 * 3)]
 
 
 class pft_step(ctypes.Structure):
@@ -178,10 +180,12 @@ class Params:
     model: int = 0
     B: float = 0.0
     storage: int = 0
+    bc: tuple = (0, 0, 0)
 
     def c(self) -> pft_params:
         return pft_params(self.nx, self.ny, self.nz, self.lx, self.ly, self.lz, self.ns, self.f,
-                          self.chiN, self.C, self.precision, self.scheme, self.model, self.B, self.storage)
+                          self.chiN, self.C, self.precision, self.scheme, self.model, self.B, self.storage,
+                          (ctypes.c_int32 * 3)(*self.bc))
 
 
 class Context:

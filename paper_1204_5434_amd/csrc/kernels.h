@@ -82,27 +82,81 @@ struct ZShape {
     static constexpr int kLds = (N2 == 1) ? 0 : kLines * N1 * (N2 + 1);  // elements
 };
 
-template <typename T, int N1, int N2, int W>
+// Walls along a line (EXT = 1 reflecting, 2 absorbing): the kernel runs on the
+// mirror image of the physical line of NP = N/2 points (even image for
+// reflecting, odd image for absorbing walls), which the periodic diffusion of
+// period 2L keeps even / odd: point n of the image is physical point
+// ext_index(n) with ext_sign(n); field tables are even images whatever the
+// wall; only the physical half is stored.
+template <int EXT, int N>
+__device__ __forceinline__ int ext_index(int n)
+{
+    if constexpr (EXT == 0) return n;
+    else return n < N / 2 ? n : N - 1 - n;
+}
+template <int EXT, int N, typename T>
+__device__ __forceinline__ T ext_sign(int n)
+{
+    return (EXT == 2 && n >= N / 2) ? T(-1) : T(1);
+}
+
+template <typename T, int N1, int N2, int W, int EXT = 0>
 __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T>* sh)
 {
     constexpr int N = N1 * N2;
+    constexpr int NP = EXT ? N / 2 : N;  // physical points per line
     constexpr int LPW = ZShape<N1, N2, W>::kLines;
     const int tid = threadIdx.x;
     const int t = tid % N2, l = tid / N2;
     const int64_t line = (int64_t)bid * LPW + l;
     const bool act = line < A.nlines;
-    const int64_t base = line * N + t;
+    const int64_t base = line * NP + (EXT ? 0 : t);
     const LayZ<N1, N2> lay{l};
 
+    // propagator-like arrays (odd images on absorbing walls)
     auto load = [&](const cx<T>* p, cx<T>(&r)[N1]) {
         if (act) {
-            sfor<0, N1>([&](auto I) { r[decltype(I)::value] = p[base + decltype(I)::value * N2]; });
+            if constexpr (EXT == 0) {
+                sfor<0, N1>([&](auto I) { r[decltype(I)::value] = p[base + decltype(I)::value * N2]; });
+            } else {
+                sfor<0, N1>([&](auto I) {
+                    const int n = decltype(I)::value * N2 + t;
+                    r[decltype(I)::value] = ext_sign<EXT, N, T>(n) * p[base + ext_index<EXT, N>(n)];
+                });
+            }
+        } else {
+            sfor<0, N1>([&](auto I) { r[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+        }
+    };
+    // field tables (even images)
+    auto load_e = [&](const cx<T>* p, cx<T>(&r)[N1]) {
+        if constexpr (EXT == 0) {
+            load(p, r);
+        } else if (act) {
+            sfor<0, N1>([&](auto I) { r[decltype(I)::value] = p[base + ext_index<EXT, N>(decltype(I)::value * N2 + t)]; });
         } else {
             sfor<0, N1>([&](auto I) { r[decltype(I)::value] = cx<T>{T(0), T(0)}; });
         }
     };
     auto store = [&](cx<T>* p, const cx<T>(&r)[N1]) {
-        if (act) sfor<0, N1>([&](auto I) { p[base + decltype(I)::value * N2] = r[decltype(I)::value]; });
+        if (!act) return;
+        if constexpr (EXT == 0) {
+            sfor<0, N1>([&](auto I) { p[base + decltype(I)::value * N2] = r[decltype(I)::value]; });
+        } else {
+            sfor<0, N1>([&](auto I) {
+                const int n = decltype(I)::value * N2 + t;
+                if (n < NP) p[base + n] = r[decltype(I)::value];
+            });
+        }
+    };
+    // one value of a propagator-like array at this lane's point i
+    auto at = [&](const cx<T>* p, int i) -> cx<T> {
+        if constexpr (EXT == 0) {
+            return p[base + i * N2];
+        } else {
+            const int n = i * N2 + t;
+            return ext_sign<EXT, N, T>(n) * p[base + ext_index<EXT, N>(n)];
+        }
     };
 
     cx<T> q[N1];
@@ -115,21 +169,21 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
             if (A.hcap) store(A.hcap, q);
             constexpr T third = T(1.0 / 3.0);
             if (A.Ep) {
-                load(A.Ep, e);
+                load_e(A.Ep, e);
                 have_e = true;
             }
             if (act) {
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
-                    q[i] = third * (T(4) * u - A.V[base + i * N2]);
+                    q[i] = third * (T(4) * u - at(A.V, i));
                 });
             }
         } else {
             load(A.V, q);
             if (A.hcap) store(A.hcap, q);
             if (A.Ep) {
-                load(A.Ep, e);
+                load_e(A.Ep, e);
                 have_e = true;
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
@@ -140,7 +194,10 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
     } else if (A.qin) {
         load(A.qin, q);
     } else {
-        sfor<0, N1>([&](auto I) { q[decltype(I)::value] = cx<T>{T(1), T(0)}; });
+        // q = 1: its image is odd across an absorbing wall
+        sfor<0, N1>([&](auto I) {
+            q[decltype(I)::value] = ext_sign<EXT, N, T>(decltype(I)::value * N2 + t) * cx<T>{T(1), T(0)};
+        });
     }
     if (A.qout) store(A.qout, q);
 
@@ -148,7 +205,7 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
         // q <- E4 q (half path start) and w <- E4 E4 q (full path start)
         cx<T> w[N1];
         if (A.En) {
-            if (!(have_e && A.En == A.Ep)) load(A.En, e);
+            if (!(have_e && A.En == A.Ep)) load_e(A.En, e);
             sfor<0, N1>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 q[i] = q[i] * e[i];
@@ -172,6 +229,14 @@ __global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads), MW) void k_zpass(ZAr
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     zpass_body<T, N1, N2, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
+// Walled z lines: the mirror image of NP = N1 N2 / 2 physical points.
+template <typename T, int N1, int N2, int EXT>
+__global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_zpass_walls(ZArgs<T> A)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    zpass_body<T, N1, N2, 1, EXT>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 // Batched: blockIdx.y selects a replica whose arguments come from a table.
@@ -221,28 +286,42 @@ struct SShape {
 };
 
 // AXIS: 0 = x (field multiplies allowed), 1 = y.
-template <typename T, int N1, int N2, int AXIS, int W>
+template <typename T, int N1, int N2, int AXIS, int W, int EXT = 0>
 __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T>* sh)
 {
+    constexpr int N = N1 * N2;
+    constexpr int NP = EXT ? N / 2 : N;  // physical points per line (walls: mirror image)
     constexpr int TC = SShape<T, N2, W>::kCols;
     const int tid = threadIdx.x;
     const int c = tid % TC, t = tid / TC;
     const int slab = bid / A.ntiles, tile = bid % A.ntiles;
     const int col = tile * TC + c;
     const bool act = col < A.ncols;
-    const int64_t base = (int64_t)slab * A.slab_stride + col + (int64_t)t * A.S;
+    const int64_t base = (int64_t)slab * A.slab_stride + col + (EXT ? 0 : (int64_t)t * A.S);
     const int64_t step = (int64_t)N2 * A.S;
     const LayS<N2, TC> lay{c};
+    // address of this lane's point i (physical point of the image with walls)
+    auto addr = [&](int i) -> int64_t {
+        if constexpr (EXT == 0) return base + i * step;
+        else return base + (int64_t)ext_index<EXT, N>(i * N2 + t) * A.S;
+    };
 
     auto ldX = [&](const cx<T>* X, cx<T>(&a)[N1]) {
         if (act) {
-            sfor<0, N1>([&](auto I) { a[decltype(I)::value] = X[base + decltype(I)::value * step]; });
+            sfor<0, N1>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                a[i] = ext_sign<EXT, N, T>(i * N2 + t) * X[addr(i)];
+            });
         } else {
             sfor<0, N1>([&](auto I) { a[decltype(I)::value] = cx<T>{T(0), T(0)}; });
         }
     };
     auto stX = [&](cx<T>* X, const cx<T>(&a)[N1]) {
-        if (act) sfor<0, N1>([&](auto I) { X[base + decltype(I)::value * step] = a[decltype(I)::value]; });
+        if (act)
+            sfor<0, N1>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if (EXT == 0 || i * N2 + t < NP) X[addr(i)] = a[i];
+            });
     };
     // one array: diffuse, [capture], [multiply by e2 = E4^2, diffuse again]
     auto run_on = [&](cx<T>* X, cx<T>(&a)[N1], const SOps<T>& op, const cx<T>(&e2)[N1], bool have_e2) {
@@ -254,7 +333,7 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
             } else if (act) {
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    const cx<T> e = op.e[base + i * step];
+                    const cx<T> e = op.e[addr(i)];  // field tables: even images
                     a[i] = a[i] * (e * e);
                 });
             }
@@ -280,8 +359,12 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
         return;
     }
     if (AXIS == 0 && A.opU.g1 && A.opV.g1 && A.opU.e && A.opU.e == A.opV.e) {
-        // both arrays take the same field table: read it once
-        ldX(A.opU.e, e2);
+        // both arrays take the same field table: read it once (even image)
+        if (act) {
+            sfor<0, N1>([&](auto I) { e2[decltype(I)::value] = A.opU.e[addr(decltype(I)::value)]; });
+        } else {
+            sfor<0, N1>([&](auto I) { e2[decltype(I)::value] = cx<T>{T(0), T(0)}; });
+        }
         sfor<0, N1>([&](auto I) { e2[decltype(I)::value] = e2[decltype(I)::value] * e2[decltype(I)::value]; });
         run(A.V, A.opV, e2, true);
         run(A.U, A.opU, e2, true);
@@ -297,6 +380,14 @@ __global__ __launch_bounds__((SShape<T, N2, W>::kThreads), MW) void k_spass(SArg
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     spass_body<T, N1, N2, AXIS, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
+// Walled x or y lines: the mirror image of NP = N1 N2 / 2 physical points.
+template <typename T, int N1, int N2, int AXIS, int EXT>
+__global__ __launch_bounds__((SShape<T, N2, 1>::kThreads)) void k_spass_walls(SArgs<T> A)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    spass_body<T, N1, N2, AXIS, 1, EXT>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 template <typename T, int N1, int N2, int AXIS, int W, int MW>
@@ -409,6 +500,15 @@ inline bool axis_supported(int n)
 PFT_DECLARE_LAUNCHERS(v0)
 PFT_DECLARE_LAUNCHERS(alt)
 #undef PFT_DECLARE_LAUNCHERS
+
+// Walled passes (EXT = 1 reflecting, 2 absorbing) over lines of n physical
+// points: the kernels of axis length 2n run on the mirror images.  Defined
+// for n with 2n in the axis list.
+template <typename T>
+hipError_t launch_zpass_walls(int nz, int ext, const ZArgs<T>& a, hipStream_t s);
+template <typename T>
+hipError_t launch_spass_walls(int axis, int n, int ext, int64_t ncols, SArgs<T> a, int nslabs, hipStream_t s);
+bool walls_supported(int n);
 
 // `var` selects the kernel variant of the axis length (0 = default).
 template <typename T>

@@ -1023,6 +1023,14 @@ struct Work {
     hipStream_t stream = nullptr;  // NULL: the context's stream
 };
 
+// The z pass on the context's grid: the mirror-image kernels on a walled z axis.
+template <typename T>
+hipError_t launch_z(const pft_ctx* c, const pft::ZArgs<T>& a, hipStream_t st)
+{
+    if (c->p.bc[2]) return pft::launch_zpass_walls<T>(c->p.nz, c->p.bc[2], a, st);
+    return pft::launch_zpass<T>(c->p.nz, c->var[2], a, st);
+}
+
 // Z pass completing step `prev` (-1: none) and starting step `next` (-1: none).
 template <typename T>
 pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout, const Work& w = Work(),
@@ -1057,8 +1065,8 @@ pft_status zpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout, 
     if (next >= 0) bytes += (rqm4 ? 2 : 1) * E + ((prev < 0 || c->kind[next] != c->kind[prev]) ? E : 0);
     if (hcap) bytes += E;
     hipStream_t st = w.stream ? w.stream : c->stream;
-    ProfScope ps(c, PFT_K_ZPASS, bytes, st, true);
-    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], a, st));
+    ProfScope ps(c, PFT_K_ZPASS, bytes, st, c->p.bc[2] == 0);
+    PFT_HIP(c, launch_z<T>(c, a, st));
     return PFT_OK;
 }
 
@@ -1078,16 +1086,22 @@ pft_status spass(pft_ctx* c, int axis, pft::SOps<T> opU, pft::SOps<T> opV, const
     if (opU.g1 && opU.e) bytes += E;
     if (opV.g1 && opV.e && !(opU.g1 && opU.e == opV.e)) bytes += E;
     hipStream_t st = w.stream ? w.stream : c->stream;
-    ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes, st, true);
+    ProfScope ps(c, axis == 0 ? PFT_K_XPASS : PFT_K_YPASS, bytes, st, c->p.bc[axis] == 0);
     const int64_t nynz = (int64_t)c->p.ny * c->p.nz;
     if (axis == 0) {
         a.S = nynz;
         a.slab_stride = 0;
-        PFT_HIP(c, pft::launch_spass<T>(0, c->p.nx, c->var[0], nynz, a, 1, st));
+        if (c->p.bc[0])
+            PFT_HIP(c, pft::launch_spass_walls<T>(0, c->p.nx, c->p.bc[0], nynz, a, 1, st));
+        else
+            PFT_HIP(c, pft::launch_spass<T>(0, c->p.nx, c->var[0], nynz, a, 1, st));
     } else {
         a.S = c->p.nz;
         a.slab_stride = nynz;
-        PFT_HIP(c, pft::launch_spass<T>(1, c->p.ny, c->var[1], c->p.nz, a, c->p.nx, st));
+        if (c->p.bc[1])
+            PFT_HIP(c, pft::launch_spass_walls<T>(1, c->p.ny, c->p.bc[1], c->p.nz, a, c->p.nx, st));
+        else
+            PFT_HIP(c, pft::launch_spass<T>(1, c->p.ny, c->var[1], c->p.nz, a, c->p.nx, st));
     }
     return PFT_OK;
 }
@@ -1486,7 +1500,9 @@ pft_status upload_factors(pft_ctx* c, int hid, double h)
     const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
     for (int full = 0; full < 2; ++full)
         for (int ax = 0; ax < 3; ++ax) {
-            const std::vector<T> g = axis_factors<T>(n[ax], L[ax], full ? h : h / 2);
+            // a walled axis diffuses the 2n-point mirror image with period 2L
+            const int w = c->p.bc[ax] ? 2 : 1;
+            const std::vector<T> g = axis_factors<T>(w * n[ax], w * L[ax], full ? h : h / 2);
             PFT_HIP(c, hipMemcpy(const_cast<T*>(gptr<T>(c, hid, full, ax)), g.data(), g.size() * sizeof(T),
                                  hipMemcpyHostToDevice));
         }
@@ -1535,7 +1551,7 @@ pft_status diffuse_t(pft_ctx* c, double* u, double h)
     a.has_next = 1;
     a.gh_n = gptr<T>(c, 3, 0, 2);
     a.gf_n = gptr<T>(c, 3, 1, 2);
-    PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], a, c->stream));
+    PFT_HIP(c, launch_z<T>(c, a, c->stream));
     const pft::SOps<T> none{nullptr, nullptr, nullptr};
     s = spass<T>(c, 1, none, {gptr<T>(c, 3, 1, 1), nullptr, nullptr});
     if (s) return s;
@@ -2349,7 +2365,7 @@ pft_status pft_set_concurrent_sweeps(pft_ctx* c, int32_t on)
 
 static bool fused_supported(const pft_params& p)
 {
-    if (p.ny != p.nz) return false;
+    if (p.ny != p.nz || p.bc[1] || p.bc[2]) return false;
     return p.precision == PFT_C128 ? pft::plane_supported<double>(p.ny) : pft::plane_supported<float>(p.ny);
 }
 
@@ -2392,6 +2408,10 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
         return PFT_E_INVALID;
     if (ed ? !(p.B > 0) : (!(p.f > 0.0 && p.f < 1.0) || !(p.chiN > 0))) return PFT_E_INVALID;
     if (p.storage < PFT_STORE_BOTH || p.storage > PFT_STORE_HOST) return PFT_E_INVALID;
+    for (int a = 0; a < 3; ++a) {
+        if (p.bc[a] < PFT_PERIODIC || p.bc[a] > PFT_ABSORBING) return PFT_E_INVALID;
+        if (p.bc[a] && !pft::walls_supported(a == 0 ? p.nx : a == 1 ? p.ny : p.nz)) return PFT_E_UNSUPPORTED;
+    }
     if (p.storage != PFT_STORE_BOTH && ed) return PFT_E_UNSUPPORTED;
     if (ed || p.storage != PFT_STORE_BOTH) dual = false;  // one sweep, or sweeps in sequence
     if (!pft::axis_supported(p.nx) || !pft::axis_supported(p.ny) || !pft::axis_supported(p.nz))
@@ -2410,7 +2430,7 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
     c->fused = fused_default(p);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->M = (int64_t)p.nx * p.ny * p.nz;
-    c->maxN = std::max(p.nx, std::max(p.ny, p.nz));
+    c->maxN = std::max((p.bc[0] ? 2 : 1) * p.nx, std::max((p.bc[1] ? 2 : 1) * p.ny, (p.bc[2] ? 2 : 1) * p.nz));
     c->elem = p.precision == PFT_C128 ? sizeof(cx<double>) : sizeof(cx<float>);
     c->h.resize(p.ns + 1);
     c->blk.resize(p.ns + 1);
@@ -2627,6 +2647,8 @@ pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, d
     if (!(st->dt >= 0) || !(st->lambda_plus >= 0) || !(st->lambda_minus >= 0))
         return c->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
     if (st->update != 0 && st->update != 1) return c->fail(PFT_E_INVALID, "update must be 0 or 1");
+    if (st->update == 1 && (c->p.bc[0] || c->p.bc[1] || c->p.bc[2]))
+        return c->fail(PFT_E_UNSUPPORTED, "the semi-implicit step needs a periodic box");
     if ((phi_a && !aligned16(phi_a)) || (phi_b && !aligned16(phi_b)) || (Q && !aligned16(Q)) || (H && !aligned16(H)))
         return c->fail(PFT_E_INVALID, "optional outputs must be 16-byte aligned");
     double* pa = phi_a ? phi_a : reinterpret_cast<double*>(c->phi);
@@ -2704,6 +2726,7 @@ pft_status pft_diffuse(pft_ctx* c, double* u, double h)
 pft_status pft_debug_kgrid(const pft_ctx* c, int32_t* m2)
 {
     if (!c || !m2) return PFT_E_INVALID;
+    if (c->p.bc[0] || c->p.bc[1] || c->p.bc[2]) return PFT_E_UNSUPPORTED;  // Fourier modes of a periodic box
     const int nx = c->p.nx, ny = c->p.ny, nz = c->p.nz;
     auto mode = [](int j, int n) { return j <= n / 2 ? j : j - n; };
     for (int x = 0; x < nx; ++x)
@@ -2733,6 +2756,7 @@ pft_status pft_adjoint(pft_ctx* c, const double* wp, const double* wm, int32_t c
     if (ckpt_every < 0) return c->fail(PFT_E_INVALID, "pft_adjoint: ckpt_every must be >= 0");
     if (c->p.model != PFT_DIBLOCK) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: diblock model only");
     if (c->p.storage != PFT_STORE_BOTH) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: needs both stores");
+    if (c->p.bc[0] || c->p.bc[1] || c->p.bc[2]) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: periodic box only");
     int Kc = ckpt_every;
     if (Kc == 0) Kc = (int)std::ceil(std::sqrt((double)c->K));
     Kc = std::max(1, std::min(Kc, c->K));
@@ -2791,7 +2815,9 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     for (int r = 1; r < n; ++r)
         if (params[r].precision != params[0].precision || params[r].scheme != params[0].scheme) return PFT_E_INVALID;
     for (int r = 0; r < n; ++r)
-        if (params[r].model != PFT_DIBLOCK || params[r].storage != PFT_STORE_BOTH) return PFT_E_UNSUPPORTED;
+        if (params[r].model != PFT_DIBLOCK || params[r].storage != PFT_STORE_BOTH || params[r].bc[0] ||
+            params[r].bc[1] || params[r].bc[2])
+            return PFT_E_UNSUPPORTED;
     pft_batch* b = new (std::nothrow) pft_batch();
     if (!b) return PFT_E_NOMEM;
     b->n = n;
