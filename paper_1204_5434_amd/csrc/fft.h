@@ -46,6 +46,23 @@ __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.im, -a.re}; }
 template <typename T>
 __device__ __forceinline__ cx<T> mul_pi(cx<T> a) { return {-a.im, a.re}; }
 
+// Streaming access to data that is written once and read back only much later
+// (the stored propagator slices): nontemporal, so that it does not displace the
+// arrays every pass re-reads from the caches.
+template <typename T>
+__device__ __forceinline__ void store_stream(cx<T>* p, cx<T> v)
+{
+    using V2 = T __attribute__((ext_vector_type(2)));
+    __builtin_nontemporal_store(V2{v.re, v.im}, reinterpret_cast<V2*>(p));
+}
+template <typename T>
+__device__ __forceinline__ cx<T> load_stream(const cx<T>* p)
+{
+    using V2 = T __attribute__((ext_vector_type(2)));
+    const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p));
+    return {v.x, v.y};
+}
+
 // ------------------------------------------------------ compile-time loops --
 template <int B, int E, class F>
 __device__ __forceinline__ void sfor(F&& f)

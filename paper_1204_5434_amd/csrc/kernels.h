@@ -149,6 +149,15 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
             });
         }
     };
+    // the stored slice: streamed past the caches where each store instruction
+    // writes whole 128-byte lines (partial lines would be written twice)
+    auto store_q = [&](cx<T>* p, const cx<T>(&r)[N1]) {
+        if constexpr (EXT == 0 && (N2 * sizeof(cx<T>)) % 128 == 0) {
+            if (act) sfor<0, N1>([&](auto I) { store_stream(p + base + decltype(I)::value * N2, r[decltype(I)::value]); });
+        } else {
+            store(p, r);
+        }
+    };
     // one value of a propagator-like array at this lane's point i
     auto at = [&](const cx<T>* p, int i) -> cx<T> {
         if constexpr (EXT == 0) {
@@ -199,7 +208,7 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
             q[decltype(I)::value] = ext_sign<EXT, N, T>(decltype(I)::value * N2 + t) * cx<T>{T(1), T(0)};
         });
     }
-    if (A.qout) store(A.qout, q);
+    if (A.qout) store_q(A.qout, q);
 
     if (A.has_next) {
         // q <- E4 q (half path start) and w <- E4 E4 q (full path start)

@@ -208,8 +208,8 @@ __device__ __forceinline__ void density_body(const cx<T>* __restrict__ qs, const
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
         NSum ar, ai, br, bi;
         for (int j = 0; j <= K; ++j) {
-            const cx<T> a = qs[(int64_t)j * M + x];
-            const cx<T> b = qds[(int64_t)(K - j) * M + x];
+            const cx<T> a = load_stream(qs + (int64_t)j * M + x);
+            const cx<T> b = load_stream(qds + (int64_t)(K - j) * M + x);
             const double2 p = cmul(make_double2(a.re, a.im), make_double2(b.re, b.im));
             if (j <= J) {
                 const double w = tau[j];
