@@ -41,8 +41,8 @@ def log(*a):
 
 def traffic_for(kind: str, precision: str):
     """HBM bytes per launch of a kernel kind from the committed counter summary
-    (profiles/lam128_hbm_traffic.txt), if it was taken on the current kernel
-    sources; else None."""
+    (profiles/lam128_hbm_traffic.txt), if it was taken on the current sources
+    of that kernel; else None."""
     path = os.path.join(ROOT, "profiles", "lam128_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -50,10 +50,10 @@ def traffic_for(kind: str, precision: str):
         from paper_1204_5434_amd import build
         lines = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
         rec = {ln[0]: ln[1:] for ln in lines}
-        if rec.get("source_hash", [None])[0] != build.source_hash():
-            return None
         entry = rec.get(f"{kind}:{precision}")
-        return None if entry is None else float(entry[0])
+        if entry is None or len(entry) < 3 or entry[2] != build.kernel_hash(kind):
+            return None
+        return float(entry[0])
     except Exception:
         return None
 
@@ -87,6 +87,20 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     # timed region: exactly `steps` evaluations between two events, both sweeps
     # running concurrently on two streams (the library's default)
     ms = timed(steps)
+    # the same evaluations one by one (an event pair each): median and IQR
+    per = []
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        evaluate()
+        b.record()
+        per.append((a, b))
+    torch.cuda.synchronize()
+    import numpy as np
+    each = np.array([a.elapsed_time(b) for a, b in per])
+    spread = {"median": float(np.median(each)), "q25": float(np.percentile(each, 25)),
+              "q75": float(np.percentile(each, 75))}
     by_schedule = None
     if fused:
         # the same with the other schedules, for comparison: axis passes only
@@ -98,6 +112,17 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
             by_schedule[name] = timed(steps)
         ctx.pft_set_fused_planes(fused)
         evaluate()
+    # the same evaluations replayed from a HIP graph (captured once)
+    ctx.pft_evaluate_graph(wp, wm, phiA, phiB, Q, 0)
+    ctx.pft_evaluate_graph(wp, wm, phiA, phiB, Q, 1)
+    torch.cuda.synchronize()
+    g0 = torch.cuda.Event(enable_timing=True)
+    g1 = torch.cuda.Event(enable_timing=True)
+    g0.record()
+    ctx.pft_evaluate_graph(wp, wm, phiA, phiB, Q, steps)
+    g1.record()
+    torch.cuda.synchronize()
+    ms_graph = g0.elapsed_time(g1) / steps
     # the same with both sweeps on one stream, for comparison
     ctx.pft_set_concurrent_sweeps(False)
     evaluate()
@@ -132,7 +157,8 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
                  for k, v in prof.items() if v[1] > 0}
     bytes_eval = sum(v[2] for v in prof.values()) / steps
     roof["aggregate_GB_s"] = round(bytes_eval / (ms * 1e-3) / 1e9, 1)
-    out = {"value": rate, "ms_per_step": ms, "ms_per_step_one_stream": ms_single, "roofline": roof,
+    out = {"value": rate, "ms_per_step": ms, "ms_per_evaluation_spread": spread, "ms_per_step_graph": ms_graph,
+           "ms_per_step_one_stream": ms_single, "roofline": roof,
            "kernels": breakdown, "Q": [Qv.real, Qv.imag],
            "schedule": {0: "axis", 1: "fused", 2: "fused-conjugate-sweep"}[fused]}
     if by_schedule is not None:
@@ -332,12 +358,24 @@ def batched_gain(binding, inputs, count: int, steps: int):
     return out
 
 
-def cpu_baseline(w, wp, wm, seconds: float):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, wp, wm, seconds: float, threads: int = 0):
     """The FP64 oracle on a bounded sample: forward-sweep Richardson steps of
-    the same 128^3 workload on all host threads, until `seconds` elapse."""
+    the same 128^3 workload on `threads` host threads (0: all, at most 16),
+    until `seconds` elapse."""
     import numpy as np
     from oracle import oracle
-    threads = min(len(os.sched_getaffinity(0)), 16)
+    if threads <= 0:
+        threads = min(len(os.sched_getaffinity(0)), 16)
     oracle.set_threads(threads)
     p = oracle.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, 0)
     wA, _ = oracle.block_fields(p, wp, wm)
@@ -352,7 +390,7 @@ def cpu_baseline(w, wp, wm, seconds: float):
         if el >= seconds:
             break
     return {"value": n * w.M / el, "unit": "grid-pts×steps/s", "cores": oracle.get_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(), "host_cores_visible": len(os.sched_getaffinity(0)),
             "sample": f"{n} forward-sweep Richardson steps of the {w.n[0]}^3 workload ({el:.1f} s); "
                       "the density reduction (~1% of the GPU time) is not in the sample"}
 
@@ -431,6 +469,16 @@ def main():
         res[precision] = run_precision(binding, w, wp, wm, precision, args.steps, args.warmup, scheme)
         log(f"[bench] {precision}: {res[precision]['ms_per_step']:.3f} ms/eval, "
             f"{res[precision]['value']:.3e} site-steps/s, roofline {res[precision]['roofline']}")
+    other = None
+    if not args.no_edwards:
+        oname = "split2" if args.scheme == "rqm4" else "rqm4"
+        osch = binding.PFT_SPLIT2 if oname == "split2" else binding.PFT_RQM4
+        other = {"scheme": oname}
+        for precision in precisions:
+            r = run_precision(binding, w, wp, wm, precision, args.steps, args.warmup, osch)
+            other[precision] = {"ms_per_step": r["ms_per_step"], "value": r["value"], "schedule": r["schedule"],
+                                "roofline_frac": r["roofline"]["frac"], "kernel": r["roofline"]["kernel"]}
+        log(f"[bench] other scheme: {other}")
     storage = None
     if not args.no_edwards:
         log("[bench] storage modes: q only in HBM, q staged in host memory")
@@ -457,10 +505,13 @@ def main():
         batched = batched_gain(binding, inputs, args.batch_replicas, args.batch_steps)
         log(f"[bench] batched: {batched}")
     cpu = None
+    cpu1 = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
         cpu = cpu_baseline(w, wp_np, wm_np, args.cpu_seconds)
         log(f"[bench] cpu baseline: {cpu}")
+        cpu1 = cpu_baseline(w, wp_np, wm_np, max(3.0, args.cpu_seconds / 3), threads=1)
+        log(f"[bench] cpu baseline, one thread: {cpu1}")
     main_ = res["f64"] if "f64" in res else res["f32"]
     line = {
         "metric": METRIC,
@@ -471,6 +522,8 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": main_["ms_per_step"],
         "ms_per_step_one_stream": main_["ms_per_step_one_stream"],
+        "ms_per_step_graph": main_["ms_per_step_graph"],
+        "ms_per_evaluation_spread": main_["ms_per_evaluation_spread"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -480,6 +533,7 @@ def main():
                    "chiN": w.chiN, "scheme": args.scheme, "site_steps_per_step": 2 * w.M * w.ns},
         "roofline": main_["roofline"],
         "cpu_baseline": cpu,
+        "cpu_baseline_one_thread": cpu1,
         "kernels": main_["kernels"],
         "schedule": main_["schedule"],
     }
@@ -497,11 +551,15 @@ def main():
         line["storage_modes"] = storage
     if walls is not None:
         line["walls"] = walls
+    if other is not None:
+        line["other_scheme"] = other
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],
                         "dtype": "f32 propagators, f64 sums", "roofline": res["f32"]["roofline"],
-                        "kernels": res["f32"]["kernels"], "schedule": res["f32"]["schedule"]}
+                        "kernels": res["f32"]["kernels"], "schedule": res["f32"]["schedule"],
+                        "ms_per_step_graph": res["f32"]["ms_per_step_graph"],
+                        "ms_per_evaluation_spread": res["f32"]["ms_per_evaluation_spread"]}
         if "ms_per_step_by_schedule" in res["f32"]:
             line["fp32"]["ms_per_step_by_schedule"] = res["f32"]["ms_per_step_by_schedule"]
     print(json.dumps(line))

@@ -206,6 +206,21 @@ pft_status pft_propagate(pft_ctx* ctx, const double* w_plus, const double* w_min
  * Errors: PFT_E_INVALID, PFT_E_STATE (no propagate yet). */
 pft_status pft_densities(pft_ctx* ctx, double* phi_a, double* phi_b, double* Q);
 
+/* pft_propagate followed by pft_densities on these buffers, replayed from a
+ * HIP graph: the first call (and any call with other buffers) captures one
+ * evaluation, both sweeps' streams included, into a graph the context owns;
+ * every call then enqueues nreps replays (0: capture only) after the work
+ * already on the context stream, and later work on that stream waits for them.
+ * The graph reads w_plus / w_minus and writes phi_a / phi_b / Q at the
+ * addresses it was captured with, so their contents may change between
+ * calls.  Replays of one context run one after another; the state afterwards
+ * is that of a plain pft_propagate + pft_densities.  Arguments and layouts as
+ * for those two calls.  Errors: PFT_E_INVALID; PFT_E_UNSUPPORTED unless both
+ * stores are in device memory (storage 0); PFT_E_STATE while profiling;
+ * PFT_E_DEVICE if capture or instantiation fails. */
+pft_status pft_evaluate_graph(pft_ctx* ctx, const double* w_plus, const double* w_minus, double* phi_a, double* phi_b,
+                              double* Q, int32_t nreps);
+
 /* Hamiltonian of Eq. (3) on the grid, H = C dV sum_x [w_-^2/chiN - i w_+]
  * - C V Log Q (principal branch), with Q from the last pft_propagate (which
  * must have used these fields).  H, h_intensive (= H / (C V)): 2 doubles out

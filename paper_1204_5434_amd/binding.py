@@ -35,7 +35,7 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_profile_end", "pft_copy_probe", "pft_adjoint", "pft_batch_create", "pft_batch_destroy",
            "pft_batch_last_error", "pft_batch_evaluate", "pft_batch_cl_steps", "pft_batch_sync",
            "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant", "pft_set_concurrent_sweeps",
-           "pft_set_fused_planes", "pft_fused_planes")
+           "pft_set_fused_planes", "pft_fused_planes", "pft_evaluate_graph")
 
 # Kernel variants per axis length (variant 0 always exists), at most MAX_VARIANTS.
 MAX_VARIANTS = 4
@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
             "pft_num_steps": (i32, [vp]),
             "pft_propagate": (i32, [vp, vp, vp]),
             "pft_densities": (i32, [vp, vp, vp, vp]),
+            "pft_evaluate_graph": (i32, [vp, vp, vp, vp, vp, vp, i32]),
             "pft_hamiltonian": (i32, [vp, vp, vp, vp, vp]),
             "pft_cl_step": (i32, [vp, vp, vp, P(pft_step), vp, vp, vp, vp]),
             "pft_node_q": (i32, [vp, vp]),
@@ -232,6 +233,11 @@ class Context:
     def pft_densities(self, phi_a, phi_b, Q=None):
         self._check(load().pft_densities(self._h, _field(phi_a, self.shape, "phi_a"),
                                          _field(phi_b, self.shape, "phi_b"), _opt(Q, (1,), "Q")))
+
+    def pft_evaluate_graph(self, w_plus, w_minus, phi_a, phi_b, Q=None, nreps: int = 1):
+        self._check(load().pft_evaluate_graph(self._h, _field(w_plus, self.shape, "w_plus"), self._wm(w_minus),
+                                              _field(phi_a, self.shape, "phi_a"),
+                                              _field(phi_b, self.shape, "phi_b"), _opt(Q, (1,), "Q"), int(nreps)))
 
     def pft_hamiltonian(self, w_plus, w_minus, H, h_intensive=None):
         self._check(load().pft_hamiltonian(self._h, _field(w_plus, self.shape, "w_plus"),

@@ -34,6 +34,28 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+# The files each kernel kind is compiled from (for staleness checks of
+# per-kernel measurements such as HBM counter traffic).
+KERNEL_FILES = {
+    "axis": ["fft.h", "kernels.h", "passes.inc", "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip",
+             "passes_f32_alt.hip"],
+    "yzpass": ["fft.h", "kernels.h", "planes.h", "planes.inc", "planes_f64.hip", "planes_f32.hip"],
+    "density": ["fft.h", "kernels.h", "pft.hip"],
+}
+KIND_GROUP = {"zpass": "axis", "ypass": "axis", "xpass": "axis", "yzpass": "yzpass", "density": "density"}
+
+
+def kernel_hash(kind: str) -> str:
+    """Hash of the sources one kernel kind (zpass, ypass, xpass, yzpass,
+    density) is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_FILES[KIND_GROUP[kind]]:
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src.replace(".hip", ".o"))
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]

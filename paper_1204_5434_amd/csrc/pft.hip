@@ -915,6 +915,13 @@ struct pft_ctx {
     void* adj = nullptr;
     double2* adjG = nullptr;    // [A sum][A comp][B sum][B comp], M each
     double2* adjAcc = nullptr;  // [3][nparts] box-derivative partials
+    // graph replay of one evaluation (pft_evaluate_graph): captured on gs for
+    // the buffers in gkey, replayed there between two events
+    hipStream_t gs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev_g0 = nullptr, ev_g1 = nullptr;
+    const void* gkey[5] = {};
     // profiling: event pairs recorded around each launch while prof is set
     bool prof = false;
     std::vector<hipEvent_t> ev;
@@ -1835,6 +1842,20 @@ int body_passes(const pft_ctx* c, int j, int axis[3], pft::SArgs<T> out[3])
 
 void free_all(pft_ctx* c)
 {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    if (c->gs) {
+        (void)hipStreamSynchronize(c->gs);
+        (void)hipStreamDestroy(c->gs);
+        c->gs = nullptr;
+    }
+    for (hipEvent_t* e : {&c->ev_g0, &c->ev_g1})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();
     if (c->s2) (void)hipStreamDestroy(c->s2);
@@ -2556,6 +2577,66 @@ pft_status pft_densities(pft_ctx* c, double* phi_a, double* phi_b, double* Q)
         return c->fail(PFT_E_INVALID, "phi_a/phi_b must be non-null and 16-byte aligned (Q aligned if given)");
     if (!c->propagated) return c->fail(PFT_E_STATE, "pft_densities needs a prior pft_propagate");
     return c->p.precision == PFT_C128 ? densities_t<double>(c, phi_a, phi_b, Q) : densities_t<float>(c, phi_a, phi_b, Q);
+}
+
+pft_status pft_evaluate_graph(pft_ctx* c, const double* wp, const double* wm, double* phi_a, double* phi_b, double* Q,
+                              int32_t nreps)
+{
+    if (!c) return PFT_E_INVALID;
+    if (nreps < 0) return c->fail(PFT_E_INVALID, "nreps must be >= 0");
+    if (c->p.storage != PFT_STORE_BOTH)
+        return c->fail(PFT_E_UNSUPPORTED, "graph replay needs both stores in device memory (storage 0)");
+    if (c->prof) return c->fail(PFT_E_STATE, "graph replay is not available while profiling");
+    const bool need_wm = c->p.model != PFT_EDWARDS;
+    if (!aligned16(wp) || (need_wm && !aligned16(wm)) || !aligned16(phi_a) || !aligned16(phi_b) || (Q && !aligned16(Q)))
+        return c->fail(PFT_E_INVALID, "w_plus/w_minus/phi_a/phi_b must be non-null and 16-byte aligned (Q aligned if given)");
+    const void* key[5] = {wp, need_wm ? wm : nullptr, phi_a, phi_b, Q};
+    if (!c->gexec || std::memcmp(key, c->gkey, sizeof key) != 0) {
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        if (c->graph) (void)hipGraphDestroy(c->graph);
+        c->gexec = nullptr;
+        c->graph = nullptr;
+        if (!c->gs) {
+            if (hipStreamCreateWithFlags(&c->gs, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_g0, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_g1, hipEventDisableTiming) != hipSuccess) {
+                (void)hipGetLastError();
+                return c->fail(PFT_E_DEVICE, "graph replay: cannot create its stream and events");
+            }
+        }
+        // capture one evaluation with the capture stream standing in for the
+        // context stream (the conjugate sweep's stream joins through its events)
+        PFT_HIP(c, hipStreamBeginCapture(c->gs, hipStreamCaptureModeThreadLocal));
+        const hipStream_t saved = c->stream;
+        c->stream = c->gs;
+        pft_status s = pft_propagate(c, wp, wm);
+        if (s == PFT_OK) s = pft_densities(c, phi_a, phi_b, Q);
+        c->stream = saved;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->gs, &g);
+        c->propagated = false;
+        if (s != PFT_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return s != PFT_OK ? s : c->fail(PFT_E_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        }
+        if (hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            c->gexec = nullptr;
+            return c->fail(PFT_E_DEVICE, "graph instantiation failed");
+        }
+        c->graph = g;
+        std::memcpy(c->gkey, key, sizeof key);
+    }
+    if (nreps == 0) return PFT_OK;
+    PFT_HIP(c, hipEventRecord(c->ev_g0, c->stream));
+    PFT_HIP(c, hipStreamWaitEvent(c->gs, c->ev_g0, 0));
+    for (int r = 0; r < nreps; ++r) PFT_HIP(c, hipGraphLaunch(c->gexec, c->gs));
+    PFT_HIP(c, hipEventRecord(c->ev_g1, c->gs));
+    PFT_HIP(c, hipStreamWaitEvent(c->stream, c->ev_g1, 0));
+    c->propagated = true;
+    return PFT_OK;
 }
 
 pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, double* H, double* hint)
