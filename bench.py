@@ -310,6 +310,50 @@ def walls_run(binding, w, wp, wm, steps: int, warmup: int):
     return out
 
 
+def adjoint_run(binding, inputs, steps: int):
+    """The gradient workload (96^3, Ns = 128, f = 0.3, checkpoints every 11
+    steps): one reverse-mode pass (dH/dw+-, dH/dL and H) against one plain
+    evaluation (propagate + densities) of the same state, both precisions."""
+    import torch
+    w = inputs.GRAD96
+    wp, wm = (torch.from_numpy(a).to("cuda") for a in inputs.fields(w))
+    out = {"workload": w.name, "grid": list(w.n), "ns": w.ns, "f": w.f, "ckpt_every": 11}
+    for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+        ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4))
+        gp = torch.empty(w.n, dtype=torch.complex128, device="cuda")
+        gm = torch.empty_like(gp)
+        dL = torch.empty(3, dtype=torch.complex128, device="cuda")
+        H = torch.empty(1, dtype=torch.complex128, device="cuda")
+        pa = torch.empty_like(gp)
+        pb = torch.empty_like(gp)
+
+        def grad():
+            ctx.pft_adjoint(wp, wm, gp, gm, dL, H, 11)
+
+        def evaluate():
+            ctx.pft_propagate(wp, wm)
+            ctx.pft_densities(pa, pb)
+
+        res = {}
+        for label, fn in (("adjoint", grad), ("evaluation", evaluate)):
+            fn()
+            torch.cuda.synchronize()
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record()
+            for _ in range(steps):
+                fn()
+            t1.record()
+            torch.cuda.synchronize()
+            res[f"{label}_ms"] = t0.elapsed_time(t1) / steps
+        res["adjoint_over_evaluation"] = res["adjoint_ms"] / res["evaluation_ms"]
+        if ctx.pft_status_flags():
+            raise RuntimeError("device status flags set in the adjoint run")
+        out[name] = res
+        ctx.close()
+    return out
+
+
 def batched_gain(binding, inputs, count: int, steps: int):
     """Uneven replicas (grids 24-48^3, Ns 40-80): complex64 propagators, all
     replicas per launch, field steps replayed from a HIP graph -- against the
@@ -413,7 +457,7 @@ def main():
                     help="replicas in the batched-vs-plain comparison (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-edwards", action="store_true",
-                    help="skip the Edwards-model, field-update, storage-mode and walled-box timings")
+                    help="skip the side measurements (other scheme, storage modes, field update, walls, adjoint, Edwards)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the library's plain copy kernel on this many MiB (counter scale)")
     args = ap.parse_args()
@@ -494,6 +538,11 @@ def main():
         log("[bench] walled boxes: reflecting film, absorbing box")
         walls = walls_run(binding, w, wp, wm, max(2, args.steps // 4), 1)
         log(f"[bench] walls: {walls}")
+    adjoint = None
+    if not args.no_edwards:
+        log("[bench] reverse mode at 96^3, Ns = 128")
+        adjoint = adjoint_run(binding, inputs, max(2, args.steps // 4))
+        log(f"[bench] adjoint: {adjoint}")
     edwards = None
     if not args.no_edwards:
         log("[bench] Edwards homopolymer model, 128^3, Ns = 100")
@@ -553,6 +602,8 @@ def main():
         line["walls"] = walls
     if other is not None:
         line["other_scheme"] = other
+    if adjoint is not None:
+        line["adjoint"] = adjoint
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],

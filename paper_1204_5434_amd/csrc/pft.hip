@@ -18,6 +18,7 @@
 #include "kernels.h"
 #include "planes.h"
 #include "sis.h"
+#include "stress.h"
 
 using pft::cx;
 
@@ -570,60 +571,10 @@ __global__ void k_adj_final(const double2* __restrict__ G, int64_t M, const doub
 
 // Box-derivative terms of one step.  The L_a derivative of a diffusion D_h'
 // multiplies its factor by 2 k_a^2 h'/L_a, i.e. u^T dD/dL_a v = (2h'/L_a) u^T
-// (-d^2/dx_a^2) D_h' v.  S[X*3 + a] hold -d^2/dx_a^2 of the captures
-// X = B (= D_{h/2} E2 Aq), A (= D_{h/2} E4 q), C (= D_h E2 q); the matching
-// left vectors are E4 lam1, E2 Al and E2 lam1.  Per block, the three axis sums
-// are added to acc[a][block].
-template <typename T>
-struct StressArgs {
-    const cx<T>* S[9];
-    const cx<T>* lam1;
-    const cx<T>* Al;
-    const cx<T>* E4;
-    double coefB[3], coefA[3], coefC[3];
-    int rqm4;
-    int64_t M;
-    double2* acc;
-};
-
-template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_stress_dot(StressArgs<T> a)
-{
-    __shared__ double2 sh[kRedThreads];
-    NSum sr[3], si[3];
-    for (int64_t x = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; x < a.M; x += (int64_t)gridDim.x * kRedThreads) {
-        const double2 e4 = wide(a.E4[x]);
-        const double2 e2 = cmul(e4, e4);
-        const double2 l1 = wide(a.lam1[x]);
-        const double2 uC = cmul(e2, l1);
-        double2 uB = d2(0, 0), uA = d2(0, 0);
-        if (a.rqm4) {
-            uB = cmul(e4, l1);
-            uA = cmul(e2, wide(a.Al[x]));
-        }
-        for (int ax = 0; ax < 3; ++ax) {
-            double2 v = cmul(uC, wide(a.S[6 + ax][x]));
-            v = d2(a.coefC[ax] * v.x, a.coefC[ax] * v.y);
-            if (a.rqm4) {
-                const double2 b = cmul(uB, wide(a.S[ax][x]));
-                const double2 c = cmul(uA, wide(a.S[3 + ax][x]));
-                v.x += a.coefB[ax] * b.x + a.coefA[ax] * c.x;
-                v.y += a.coefB[ax] * b.y + a.coefA[ax] * c.y;
-            }
-            sr[ax].add(v.x);
-            si[ax].add(v.y);
-        }
-    }
-    for (int ax = 0; ax < 3; ++ax) {
-        const double2 s = block_sum(make_double2(sr[ax].value(), si[ax].value()), sh);
-        if (threadIdx.x == 0) {
-            double2 t = a.acc[ax * gridDim.x + blockIdx.x];
-            a.acc[ax * gridDim.x + blockIdx.x] = d2(t.x + s.x, t.y + s.y);
-        }
-        __syncthreads();
-    }
-}
-
+// (-d^2/dx_a^2) D_h' v.  The stress passes (one per axis and step) evaluate
+// these with the captures X = B (= D_{h/2} E2 Aq), A (= D_{h/2} E4 q),
+// C (= D_h E2 q) and the left vectors E4 lam1, E2 Al, E2 lam1, adding their
+// workgroup sums to acc[a][block]; sums[a] is their total.
 // dH/dL_a = C dV S / L_a - C (V/L_a) Log Q - C V (dQ/dL_a)/Q with
 // dQ/dL_a = sums[a] / M and S = sum_x [w_-^2/chiN - i w_+].
 __global__ void k_stress_final(const double2* __restrict__ sums, const double2* __restrict__ Sp,
@@ -646,16 +597,6 @@ __global__ void k_fill_zero(double2* __restrict__ p, int64_t n)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = make_double2(0.0, 0.0);
-}
-
-template <typename T>
-__global__ void k_copy(const cx<T>* __restrict__ src, cx<T>* __restrict__ d0, cx<T>* __restrict__ d1, int64_t M)
-{
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < M; x += (int64_t)gridDim.x * blockDim.x) {
-        const cx<T> v = src[x];
-        d0[x] = v;
-        d1[x] = v;
-    }
 }
 
 // ---------------------------------------------------------------- batches --
@@ -1586,7 +1527,7 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     const int64_t M = c->M;
     const bool rqm4 = c->p.scheme == PFT_RQM4;
     const int nck = (K + Kc - 1) / Kc;  // checkpoint nodes a = 0, Kc, ... < K
-    const size_t nslices = (size_t)nck + 1 + 4 * (size_t)Kc + 4 + 2 + 9;
+    const size_t nslices = (size_t)nck + 1 + 4 * (size_t)Kc + 4 + 2;
     if (!c->adj || c->adj_kc != Kc) {
         if (c->adj) (void)hipFree(c->adj);
         c->adj = nullptr;
@@ -1601,7 +1542,11 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
         c->adjG = nullptr;
         return c->fail(PFT_E_NOMEM, "pft_adjoint: cannot allocate accumulators");
     }
-    if (!c->adjAcc && hipMalloc((void**)&c->adjAcc, 3 * (size_t)c->nparts * sizeof(double2)) != hipSuccess) {
+    // stress partials: one slot per workgroup of each axis's stress pass
+    int64_t np = 1;
+    for (int ax = 0; ax < 3; ++ax)
+        np = std::max<int64_t>(np, pft::stress_blocks<T>(ax, c->p.nx, c->p.ny, c->p.nz));
+    if (!c->adjAcc && hipMalloc((void**)&c->adjAcc, 3 * (size_t)np * sizeof(double2)) != hipSuccess) {
         (void)hipGetLastError();
         c->adjAcc = nullptr;
         return c->fail(PFT_E_NOMEM, "pft_adjoint: cannot allocate stress partials");
@@ -1619,8 +1564,6 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     cx<T>* Al = sl(o++);
     cx<T>* Bl = sl(o++);
     const Work wl{sl(o), sl(o + 1)}; o += 2;
-    cx<T>* S[9];
-    for (int i = 0; i < 9; ++i) S[i] = sl(o++);
     auto seg = [&](cx<T>* buf, int i) { return buf + (size_t)i * M; };
 
     pft_status s = field_tables_t<T>(c, wp, wm);
@@ -1643,10 +1586,9 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     s = hamiltonian_launch(c, wp, wm, H ? H : reinterpret_cast<double*>(c->scal + 1), nullptr);
     if (s) return s;
     hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(4 * M, 256)), dim3(256), 0, c->stream, c->adjG, 4 * M);
-    hipLaunchKernelGGL(k_fill_zero, dim3(1), dim3(256), 0, c->stream, c->adjAcc, (int64_t)3 * c->nparts);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(3 * np, 256)), dim3(256), 0, c->stream, c->adjAcc, (int64_t)3 * np);
     PFT_HIP(c, hipGetLastError());
 
-    const pft::SOps<T> none{nullptr, nullptr, nullptr};
     auto dtab = [&](int ax) { return gptr<T>(c, 4, 0, ax); };
     const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
 
@@ -1680,48 +1622,24 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
         }
         PFT_HIP(c, hipGetLastError());
         if (dL) {
-            // -d^2/dx_a^2 of each capture X (B, A, C): z out of place, y and x on copies
-            const cx<T>* X[3] = {seg(segB, j - a), seg(segA, j - a), seg(segC, j - a)};
-            if (!rqm4) X[2] = seg(segB, j - a);  // plain split: the z-pass capture is D_h E2 q
-            for (int xi = rqm4 ? 0 : 2; xi < 3; ++xi) {
-                pft::ZArgs<T> z{};
-                z.nlines = (int64_t)c->p.nx * c->p.ny;
-                z.U = S[xi * 3 + 2];
-                z.V = S[xi * 3 + 2];
-                z.qin = X[xi];
-                z.scheme = PFT_SPLIT2;
-                z.has_next = 1;
-                z.gf_n = dtab(2);
-                PFT_HIP(c, pft::launch_zpass<T>(c->p.nz, c->var[2], z, c->stream));
-                hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(M, 256)), dim3(256), 0, c->stream, X[xi], S[xi * 3 + 1],
-                                   S[xi * 3 + 0], M);
-                PFT_HIP(c, hipGetLastError());
-            }
-            for (int ax = 0; ax < 2; ++ax) {  // x then y, two arrays per launch
-                const pft::SOps<T> op{dtab(ax), nullptr, nullptr};
-                if (rqm4) {
-                    s = spass<T>(c, ax, op, op, Work{S[0 * 3 + ax], S[1 * 3 + ax]});
-                    if (s) return s;
-                }
-                s = spass<T>(c, ax, op, none, Work{S[2 * 3 + ax], S[2 * 3 + ax]});
-                if (s) return s;
-            }
-            StressArgs<T> sa{};
-            for (int i = 0; i < 9; ++i) sa.S[i] = S[i];
-            sa.lam1 = lam[cur];
-            sa.Al = Al;
-            sa.E4 = etab<T>(c, c->kind[j]);
+            // -d^2/dx_a^2 of each capture along each axis, dotted with its partner
+            pft::StressPass<T> sp{};
+            sp.X[0] = seg(segB, j - a);
+            sp.X[1] = seg(segA, j - a);
+            sp.X[2] = rqm4 ? seg(segC, j - a) : seg(segB, j - a);  // plain split: D_h E2 q
+            sp.first = rqm4 ? 0 : 2;
+            sp.lam = lam[cur];
+            sp.Alam = Al;
+            sp.E4 = etab<T>(c, c->kind[j]);
             for (int ax = 0; ax < 3; ++ax) {
                 const double r = c->h[j] / L[ax];
-                sa.coefB[ax] = rqm4 ? 4.0 / 3.0 * r : 0.0;
-                sa.coefA[ax] = rqm4 ? 4.0 / 3.0 * r : 0.0;
-                sa.coefC[ax] = rqm4 ? -2.0 / 3.0 * r : 2.0 * r;
+                sp.coef[0] = rqm4 ? 4.0 / 3.0 * r : 0.0;
+                sp.coef[1] = rqm4 ? 4.0 / 3.0 * r : 0.0;
+                sp.coef[2] = rqm4 ? -2.0 / 3.0 * r : 2.0 * r;
+                sp.d2 = dtab(ax);
+                sp.part = c->adjAcc + (size_t)ax * np;
+                PFT_HIP(c, pft::launch_stress<T>(ax, c->p.nx, c->p.ny, c->p.nz, sp, c->stream));
             }
-            sa.rqm4 = rqm4 ? 1 : 0;
-            sa.M = M;
-            sa.acc = c->adjAcc;
-            hipLaunchKernelGGL((k_stress_dot<T>), dim3(c->nparts), dim3(kRedThreads), 0, c->stream, sa);
-            PFT_HIP(c, hipGetLastError());
         }
         cur = 1 - cur;
     }
@@ -1731,7 +1649,7 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
                        reinterpret_cast<double2*>(dwp), reinterpret_cast<double2*>(dwm));
     PFT_HIP(c, hipGetLastError());
     if (dL) {
-        hipLaunchKernelGGL(k_final_sum, dim3(3), dim3(kRedThreads), 0, c->stream, c->adjAcc, c->nparts, 1.0,
+        hipLaunchKernelGGL(k_final_sum, dim3(3), dim3(kRedThreads), 0, c->stream, c->adjAcc, (int)np, 1.0,
                            c->scal + 5, (double2*)nullptr, (uint32_t*)nullptr);
         hipLaunchKernelGGL(k_stress_final, dim3(1), dim3(64), 0, c->stream, c->scal + 5, c->scal + 4, c->scal,
                            c->p.C, c->p.lx, c->p.ly, c->p.lz, M, reinterpret_cast<double2*>(dL));
