@@ -147,8 +147,9 @@ pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
 /* The q and q-dagger sweeps are independent; by default the q-dagger sweep of
  * pft_propagate runs on a second (default-priority) stream with its own work
  * arrays, forked from and joined back to the context stream, so the memory
- * phases of one overlap the on-chip transform phases of the other.  on = 0
- * runs both on the context stream.  Errors: PFT_E_INVALID. */
+ * phases of one overlap the on-chip transform phases of the other (and
+ * pft_adjoint recomputes its next segment there).  on = 0 runs everything on
+ * the context stream.  Errors: PFT_E_INVALID. */
 pft_status pft_set_concurrent_sweeps(pft_ctx* ctx, int32_t on);
 
 /* Schedule of the sweeps (Eq. (12) either way; results agree to rounding).
@@ -236,11 +237,13 @@ pft_status pft_cl_step(pft_ctx* ctx, double* w_plus, double* w_minus, const pft_
 
 /* Reverse-mode derivatives of H (Eq. (3)) through the K discrete split steps
  * of the context's scheme, with q checkpointed every ckpt_every nodes
- * (0: ceil(sqrt(K))) and each segment recomputed once: memory ~(5 sqrt(K) + 15)
- * extra fields instead of K.  The adjoint vector of step j is the conjugate
- * propagator (every split step is complex-symmetric), so this is one
- * checkpointed forward sweep, one segment recompute and one q-dagger sweep
- * with per-step accumulation in FP64 (Neumaier).
+ * (0: ceil(sqrt(K))) and each segment recomputed once: memory ~(9 sqrt(K) + 6)
+ * extra fields instead of K (~(5 sqrt(K) + 6) with concurrent sweeps off).  The
+ * adjoint vector of step j is the conjugate propagator (every split step is
+ * complex-symmetric), so this is one checkpointed forward sweep, one segment
+ * recompute (on the second stream, one segment ahead, while concurrent sweeps
+ * are on) and one q-dagger sweep with per-step accumulation in FP64 (Neumaier).
+ * The box derivatives take one stress pass per axis and step.
  * Outputs (device): dH_dwplus, dH_dwminus -- [nx][ny][nz] complex128, the
  * holomorphic derivative dH/dw at each grid point (not per unit volume);
  * dH_dL -- 3 complex128 (may be NULL): dH/dL_x, dH/dL_y, dH/dL_z with each box

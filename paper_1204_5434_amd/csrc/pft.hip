@@ -853,7 +853,9 @@ struct pft_ctx {
     // reverse mode: working-precision slices and FP64 accumulators, allocated
     // on the first pft_adjoint call for its checkpoint interval
     int adj_kc = 0;
+    size_t adj_slices = 0;
     void* adj = nullptr;
+    hipEvent_t ev_adj[5] = {};  // segment buffer ready (2), buffer free, spare, checkpoints done
     double2* adjG = nullptr;    // [A sum][A comp][B sum][B comp], M each
     double2* adjAcc = nullptr;  // [3][nparts] box-derivative partials
     // graph replay of one evaluation (pft_evaluate_graph): captured on gs for
@@ -1527,16 +1529,29 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     const int64_t M = c->M;
     const bool rqm4 = c->p.scheme == PFT_RQM4;
     const int nck = (K + Kc - 1) / Kc;  // checkpoint nodes a = 0, Kc, ... < K
-    const size_t nslices = (size_t)nck + 1 + 4 * (size_t)Kc + 4 + 2;
-    if (!c->adj || c->adj_kc != Kc) {
+    // the segment buffers are doubled when the next segment's recomputation
+    // runs on the second stream beside the current segment's adjoint steps
+    const bool conc = c->s2 && !c->dual_off && nck > 1;
+    const int nbuf = conc ? 2 : 1;
+    const size_t nslices = (size_t)nck + 1 + 4 * (size_t)nbuf * Kc + 4 + 2;
+    if (!c->adj || c->adj_kc != Kc || c->adj_slices != nslices) {
         if (c->adj) (void)hipFree(c->adj);
         c->adj = nullptr;
         if (hipMalloc(&c->adj, nslices * M * c->elem) != hipSuccess) {
             (void)hipGetLastError();
+            c->adj_kc = 0;
+            c->adj_slices = 0;
             return c->fail(PFT_E_NOMEM, "pft_adjoint: cannot allocate %zu slices", nslices);
         }
         c->adj_kc = Kc;
+        c->adj_slices = nslices;
     }
+    for (hipEvent_t* e : {&c->ev_adj[0], &c->ev_adj[1], &c->ev_adj[2], &c->ev_adj[3], &c->ev_adj[4]})
+        if (!*e && hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            *e = nullptr;
+            return c->fail(PFT_E_DEVICE, "pft_adjoint: cannot create events");
+        }
     if (!c->adjG && hipMalloc((void**)&c->adjG, 4 * M * sizeof(double2)) != hipSuccess) {
         (void)hipGetLastError();
         c->adjG = nullptr;
@@ -1556,10 +1571,22 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     auto ckpt = [&](int node) { return sl((size_t)(node / Kc)); };
     cx<T>* qK = sl(nck);
     size_t o = nck + 1;
-    cx<T>* segQ = sl(o); o += Kc;  // segQ[i] = q_{a+1+i}
-    cx<T>* segA = sl(o); o += Kc;
-    cx<T>* segB = sl(o); o += Kc;
-    cx<T>* segC = sl(o); o += Kc;
+    cx<T>* segQ[2];  // segQ[buf][i] = q_{a+1+i}
+    cx<T>* segA[2];
+    cx<T>* segB[2];
+    cx<T>* segC[2];
+    for (int bf = 0; bf < nbuf; ++bf) {
+        segQ[bf] = sl(o); o += Kc;
+        segA[bf] = sl(o); o += Kc;
+        segB[bf] = sl(o); o += Kc;
+        segC[bf] = sl(o); o += Kc;
+    }
+    if (nbuf == 1) {
+        segQ[1] = segQ[0];
+        segA[1] = segA[0];
+        segB[1] = segB[0];
+        segC[1] = segC[0];
+    }
     cx<T>* lam[2] = {sl(o), sl(o + 1)}; o += 2;
     cx<T>* Al = sl(o++);
     cx<T>* Bl = sl(o++);
@@ -1592,28 +1619,64 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     auto dtab = [&](int ax) { return gptr<T>(c, 4, 0, ax); };
     const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
 
+    // Segment sg covers steps [sg Kc, min(sg Kc + Kc, K)) and uses buffer
+    // sg % 2.  Its recomputation (forward from its checkpoint, storing q and
+    // the captures of each step) runs on the recompute stream rs, the next
+    // lower segment's while this one's adjoint steps run on the context stream.
+    const hipStream_t rs = conc ? c->s2 : c->stream;
+    const Work wr{c->U, c->V, rs};
+    auto recompute = [&](int sg) -> pft_status {
+        const int a0 = sg * Kc, b0 = std::min(a0 + Kc, K), bf = sg % 2;
+        pft_status e = zpass<T>(c, -1, a0, ckpt(a0), nullptr, wr);
+        if (e) return e;
+        for (int jj = a0; jj < b0; ++jj) {
+            e = step_body<T>(c, jj, wr, rqm4 ? seg(segA[bf], jj - a0) : nullptr, rqm4 ? seg(segC[bf], jj - a0) : nullptr);
+            if (e) return e;
+            e = zpass<T>(c, jj, jj + 1 < b0 ? jj + 1 : -1, nullptr, seg(segQ[bf], jj - a0), wr, seg(segB[bf], jj - a0));
+            if (e) return e;
+        }
+        PFT_HIP(c, hipEventRecord(c->ev_adj[bf], rs));  // ready
+        return PFT_OK;
+    };
+    if (conc) {
+        // the checkpoints are complete: start the last segment's recomputation
+        PFT_HIP(c, hipEventRecord(c->ev_adj[4], c->stream));
+        PFT_HIP(c, hipStreamWaitEvent(rs, c->ev_adj[4], 0));
+        if ((s = recompute(nck - 1))) return s;
+    }
+
     // lambda_K = 1, then the steps in reverse order
     s = zpass<T>(c, -1, K - 1, nullptr, lam[0], wl);
     if (s) return s;
     int cur = 0;
     for (int j = K - 1; j >= 0; --j) {
         const int a = (j / Kc) * Kc, b = std::min(a + Kc, K);
+        const int sg = j / Kc, bf = sg % 2;
         if (j == b - 1) {
-            s = zpass<T>(c, -1, a, ckpt(a), nullptr);
-            if (s) return s;
-            for (int jj = a; jj < b; ++jj) {
-                s = step_body<T>(c, jj, Work(), rqm4 ? seg(segA, jj - a) : nullptr, rqm4 ? seg(segC, jj - a) : nullptr);
-                if (s) return s;
-                s = zpass<T>(c, jj, jj + 1 < b ? jj + 1 : -1, nullptr, seg(segQ, jj - a), Work(), seg(segB, jj - a));
-                if (s) return s;
+            if (!conc) {
+                // one buffer on one stream: recompute this segment in place
+                if ((s = recompute(sg))) return s;
+            } else {
+                PFT_HIP(c, hipStreamWaitEvent(c->stream, c->ev_adj[bf], 0));
+                if (sg > 0) {
+                    // the next lower segment reuses the buffer of the segment
+                    // above this one, whose adjoint steps are all enqueued
+                    PFT_HIP(c, hipEventRecord(c->ev_adj[2], c->stream));
+                    PFT_HIP(c, hipStreamWaitEvent(rs, c->ev_adj[2], 0));
+                    if ((s = recompute(sg - 1))) return s;
+                }
             }
         }
+        cx<T>* const sQ = segQ[bf];
+        cx<T>* const sA = segA[bf];
+        cx<T>* const sB = segB[bf];
+        cx<T>* const sC = segC[bf];
         s = step_body<T>(c, j, wl, rqm4 ? Al : nullptr, nullptr);
         if (s) return s;
         s = zpass<T>(c, j, j > 0 ? j - 1 : -1, nullptr, lam[1 - cur], wl, rqm4 ? Bl : nullptr);
         if (s) return s;
-        const cx<T>* q0 = (j == a) ? ckpt(a) : seg(segQ, j - a - 1);
-        AccArgs<T> ac{lam[cur], lam[1 - cur], Al, Bl, q0, seg(segQ, j - a), seg(segA, j - a), seg(segB, j - a),
+        const cx<T>* q0 = (j == a) ? ckpt(a) : seg(sQ, j - a - 1);
+        AccArgs<T> ac{lam[cur], lam[1 - cur], Al, Bl, q0, seg(sQ, j - a), seg(sA, j - a), seg(sB, j - a),
                       etab<T>(c, c->kind[j]), c->h[j], rqm4 ? 1 : 0, M,
                       c->adjG + (c->blk[j] == 0 ? 0 : 2 * M), c->adjG + (c->blk[j] == 0 ? M : 3 * M)};
         {
@@ -1624,9 +1687,9 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
         if (dL) {
             // -d^2/dx_a^2 of each capture along each axis, dotted with its partner
             pft::StressPass<T> sp{};
-            sp.X[0] = seg(segB, j - a);
-            sp.X[1] = seg(segA, j - a);
-            sp.X[2] = rqm4 ? seg(segC, j - a) : seg(segB, j - a);  // plain split: D_h E2 q
+            sp.X[0] = seg(sB, j - a);
+            sp.X[1] = seg(sA, j - a);
+            sp.X[2] = rqm4 ? seg(sC, j - a) : seg(sB, j - a);  // plain split: D_h E2 q
             sp.first = rqm4 ? 0 : 2;
             sp.lam = lam[cur];
             sp.Alam = Al;
@@ -1773,6 +1836,11 @@ void free_all(pft_ctx* c)
         if (*e) {
             (void)hipEventDestroy(*e);
             *e = nullptr;
+        }
+    for (hipEvent_t& e : c->ev_adj)
+        if (e) {
+            (void)hipEventDestroy(e);
+            e = nullptr;
         }
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     c->ev.clear();

@@ -80,6 +80,13 @@ def test_checkpoint_interval_is_exact(scheme):
         got = gpu_adjoint(ctx, dev(wp), dev(wm), kc=kc)
         for a, b in zip(got[:3], ref[:3]):
             assert np.array_equal(a, b), kc
+    # segments recomputed in place on one stream instead of beside the
+    # adjoint steps on a second one: the same numbers
+    ctx.pft_set_concurrent_sweeps(False)
+    for kc in (2, 7):
+        got = gpu_adjoint(ctx, dev(wp), dev(wm), kc=kc)
+        for a, b in zip(got[:3], ref[:3]):
+            assert np.array_equal(a, b), ("one stream", kc)
 
 
 def test_split2_gradient_is_the_force():
