@@ -80,10 +80,10 @@ typedef struct {
  * transforms for periodic, Neumann and Dirichlet boundaries).  Walls sit half a
  * cell outside the grid points x_n = (n + 1/2) L / N.  PFT_REFLECTING: zero
  * normal derivative (cosine modes, decay exp(-(pi m / L)^2 h), m = 0..N-1);
- * PFT_ABSORBING: q = 0 on the walls (sine modes, m = 1..N).  A walled axis of
- * N points runs the periodic kernels of length 2N on the even (reflecting) or
- * odd (absorbing) mirror image of each line, so N must be one of 8 12 16 20 24
- * 32 40 48 64 96 128 (else PFT_E_UNSUPPORTED).  Walled contexts run the axis
+ * PFT_ABSORBING: q = 0 on the walls (sine modes, m = 1..N).  A walled line of
+ * N points is diffused with one N-point transform of its even/odd-reordered
+ * points and a pairing of frequencies m and N - m, for every N of the axis
+ * list (else PFT_E_UNSUPPORTED).  Walled contexts run the axis
  * schedule on walled y or z axes, and pft_adjoint, pft_debug_kgrid, the
  * semi-implicit step and batches accept periodic boxes only
  * (PFT_E_UNSUPPORTED). */

@@ -387,6 +387,82 @@ __device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict
     }
 }
 
+// ------------------------------------------------- diffusion between walls --
+// A line of N points between walls (Sec. III: cosine modes for reflecting,
+// sine modes for absorbing walls) is held in the order v[n] = x[2n] for
+// n < N/2 and v[n] = x[2(N-1-n)+1] for n >= N/2, absorbing walls with the
+// sign of the odd points x flipped.  One N-point DFT V of v then carries the
+// cosine coefficients of x as C[m] = (w_m V[m] + conj(w_m) V[N-m]) / 2,
+// w_m = exp(-i pi m / 2N), so multiplying each mode by g_m and transforming
+// back is, per frequency,
+//   V'[m] = alpha_m V[m] + beta_m V[(N-m) mod N],
+//   alpha_m = (g_m + g_{N-m}) / 2,  beta_m = (g_m - g_{N-m}) exp(i pi m / N) / 2
+// (alpha_0 = g_0, beta_0 = 0; absorbing walls use g_m of sine mode N - m).
+// ab holds (alpha_m, Re beta_m, Im beta_m) for m = 0..N-1 with 1/N folded in.
+// The pairing of m with N - m crosses lanes, so the stage-two spectrum goes
+// through LDS once more than in diffuse(); same calling rules as diffuse().
+template <int N1, int N2, typename T, class Lay>
+__device__ __forceinline__ void pair_diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay,
+                                             const T* __restrict__ ab)
+{
+    constexpr int N = N1 * N2;
+    auto mix = [&](int m, cx<T> z, cx<T> zp) -> cx<T> {
+        const T al = ab[3 * m];
+        const cx<T> be{ab[3 * m + 1], ab[3 * m + 2]};
+        return al * z + be * zp;
+    };
+    if constexpr (N2 == 1) {
+        dft<N1, false>(a);
+        cx<T> b[N1];
+        sfor<0, N1>([&](auto K) {
+            constexpr int m = decltype(K)::value;
+            b[m] = mix(m, a[m], a[(N - m) % N]);
+        });
+        sfor<0, N1>([&](auto K) { a[decltype(K)::value] = b[decltype(K)::value]; });
+        dft<N1, true>(a);
+    } else {
+        static_assert(N1 % N2 == 0, "each lane must own whole stage-two transforms");
+        constexpr int NB = N1 / N2;
+        dft<N1, false>(a);
+        twiddle<N1, N, false>(a, t);
+        __syncthreads();
+        sfor<0, N1>([&](auto K1) { sh[lay(decltype(K1)::value, t)] = a[decltype(K1)::value]; });
+        __syncthreads();
+        // stage two forward: row k1 becomes V[k1 + N1 k2], k2 = 0..N2-1, in place
+        sfor<0, NB>([&](auto I) {
+            const int k1 = t + N2 * decltype(I)::value;
+            cx<T> b[N2];
+            sfor<0, N2>([&](auto M2) { b[decltype(M2)::value] = sh[lay(k1, decltype(M2)::value)]; });
+            dft<N2, false>(b);
+            sfor<0, N2>([&](auto K2) { sh[lay(k1, decltype(K2)::value)] = b[decltype(K2)::value]; });
+        });
+        __syncthreads();
+        // pair each frequency with N - m (row (N1 - k1) mod N1, held by another lane)
+        cx<T> z[NB][N2];
+        sfor<0, NB>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const int k1 = t + N2 * i;
+            const int k1p = (N1 - k1) % N1;
+            sfor<0, N2>([&](auto K2) {
+                constexpr int k2 = decltype(K2)::value;
+                const int k2p = (k1 == 0) ? (N2 - k2) % N2 : N2 - 1 - k2;
+                z[i][k2] = mix(k1 + N1 * k2, sh[lay(k1, k2)], sh[lay(k1p, k2p)]);
+            });
+        });
+        __syncthreads();
+        sfor<0, NB>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const int k1 = t + N2 * i;
+            dft<N2, true>(z[i]);
+            sfor<0, N2>([&](auto M2) { sh[lay(k1, decltype(M2)::value)] = z[i][decltype(M2)::value]; });
+        });
+        __syncthreads();
+        sfor<0, N1>([&](auto K1) { a[decltype(K1)::value] = sh[lay(decltype(K1)::value, t)]; });
+        twiddle<N1, N, true>(a, t);
+        dft<N1, true>(a);
+    }
+}
+
 // ------------------------------------------- one-way line transforms ------
 // line_forward: the line held as in diffuse() (lane t owns n = n1 N2 + t) is
 // replaced by its unnormalised DFT, handed out in natural order: store(k, X[k])

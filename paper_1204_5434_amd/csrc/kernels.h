@@ -82,17 +82,17 @@ struct ZShape {
     static constexpr int kLds = (N2 == 1) ? 0 : kLines * N1 * (N2 + 1);  // elements
 };
 
-// Walls along a line (EXT = 1 reflecting, 2 absorbing): the kernel runs on the
-// mirror image of the physical line of NP = N/2 points (even image for
-// reflecting, odd image for absorbing walls), which the periodic diffusion of
-// period 2L keeps even / odd: point n of the image is physical point
-// ext_index(n) with ext_sign(n); field tables are even images whatever the
-// wall; only the physical half is stored.
+// Walls along a line (EXT = 1 reflecting, 2 absorbing): register n of the
+// line holds physical point ext_index(n) (x[2n] for n < N/2, then the odd
+// points backwards), times ext_sign(n) (-1 on the odd points between
+// absorbing walls), the order in which pair_diffuse() applies the walled
+// diffusion with one N-point transform.  Field tables are read through the
+// same index without the sign.
 template <int EXT, int N>
 __device__ __forceinline__ int ext_index(int n)
 {
     if constexpr (EXT == 0) return n;
-    else return n < N / 2 ? n : N - 1 - n;
+    else return n < N / 2 ? 2 * n : 2 * (N - 1 - n) + 1;
 }
 template <int EXT, int N, typename T>
 __device__ __forceinline__ T ext_sign(int n)
@@ -100,20 +100,30 @@ __device__ __forceinline__ T ext_sign(int n)
     return (EXT == 2 && n >= N / 2) ? T(-1) : T(1);
 }
 
+// The line diffusion of the periodic (EXT = 0) or walled line.
+template <int EXT, int N1, int N2, typename T, class Lay>
+__device__ __forceinline__ void line_diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay,
+                                             const T* __restrict__ g)
+{
+    if constexpr (EXT == 0)
+        diffuse<N1, N2>(a, t, sh, lay, g);
+    else
+        pair_diffuse<N1, N2>(a, t, sh, lay, g);
+}
+
 template <typename T, int N1, int N2, int W, int EXT = 0>
 __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T>* sh)
 {
     constexpr int N = N1 * N2;
-    constexpr int NP = EXT ? N / 2 : N;  // physical points per line
     constexpr int LPW = ZShape<N1, N2, W>::kLines;
     const int tid = threadIdx.x;
     const int t = tid % N2, l = tid / N2;
     const int64_t line = (int64_t)bid * LPW + l;
     const bool act = line < A.nlines;
-    const int64_t base = line * NP + (EXT ? 0 : t);
+    const int64_t base = line * N + (EXT ? 0 : t);
     const LayZ<N1, N2> lay{l};
 
-    // propagator-like arrays (odd images on absorbing walls)
+    // propagator-like arrays (odd points sign-flipped between absorbing walls)
     auto load = [&](const cx<T>* p, cx<T>(&r)[N1]) {
         if (act) {
             if constexpr (EXT == 0) {
@@ -128,7 +138,7 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
             sfor<0, N1>([&](auto I) { r[decltype(I)::value] = cx<T>{T(0), T(0)}; });
         }
     };
-    // field tables (even images)
+    // field tables (no sign)
     auto load_e = [&](const cx<T>* p, cx<T>(&r)[N1]) {
         if constexpr (EXT == 0) {
             load(p, r);
@@ -145,7 +155,7 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
         } else {
             sfor<0, N1>([&](auto I) {
                 const int n = decltype(I)::value * N2 + t;
-                if (n < NP) p[base + n] = r[decltype(I)::value];
+                p[base + ext_index<EXT, N>(n)] = ext_sign<EXT, N, T>(n) * r[decltype(I)::value];
             });
         }
     };
@@ -174,7 +184,7 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
     if (A.has_prev) {
         if (A.scheme == kSchemeRQM4) {
             load(A.U, q);
-            diffuse<N1, N2>(q, t, sh, lay, A.gh_p);
+            line_diffuse<EXT, N1, N2>(q, t, sh, lay, A.gh_p);
             if (A.hcap) store(A.hcap, q);
             constexpr T third = T(1.0 / 3.0);
             if (A.Ep) {
@@ -203,7 +213,7 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
     } else if (A.qin) {
         load(A.qin, q);
     } else {
-        // q = 1: its image is odd across an absorbing wall
+        // q = 1 (odd points sign-flipped between absorbing walls)
         sfor<0, N1>([&](auto I) {
             q[decltype(I)::value] = ext_sign<EXT, N, T>(decltype(I)::value * N2 + t) * cx<T>{T(1), T(0)};
         });
@@ -224,10 +234,10 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
             sfor<0, N1>([&](auto I) { w[decltype(I)::value] = q[decltype(I)::value]; });
         }
         if (A.scheme == kSchemeRQM4) {
-            diffuse<N1, N2>(q, t, sh, lay, A.gh_n);
+            line_diffuse<EXT, N1, N2>(q, t, sh, lay, A.gh_n);
             store(A.U, q);
         }
-        diffuse<N1, N2>(w, t, sh, lay, A.gf_n);
+        line_diffuse<EXT, N1, N2>(w, t, sh, lay, A.gf_n);
         store(A.V, w);
     }
 }
@@ -240,7 +250,7 @@ __global__ __launch_bounds__((ZShape<N1, N2, W>::kThreads), MW) void k_zpass(ZAr
     zpass_body<T, N1, N2, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
-// Walled z lines: the mirror image of NP = N1 N2 / 2 physical points.
+// Walled z lines of N1 N2 points.
 template <typename T, int N1, int N2, int EXT>
 __global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_zpass_walls(ZArgs<T> A)
 {
@@ -299,7 +309,6 @@ template <typename T, int N1, int N2, int AXIS, int W, int EXT = 0>
 __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T>* sh)
 {
     constexpr int N = N1 * N2;
-    constexpr int NP = EXT ? N / 2 : N;  // physical points per line (walls: mirror image)
     constexpr int TC = SShape<T, N2, W>::kCols;
     const int tid = threadIdx.x;
     const int c = tid % TC, t = tid / TC;
@@ -309,7 +318,7 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
     const int64_t base = (int64_t)slab * A.slab_stride + col + (EXT ? 0 : (int64_t)t * A.S);
     const int64_t step = (int64_t)N2 * A.S;
     const LayS<N2, TC> lay{c};
-    // address of this lane's point i (physical point of the image with walls)
+    // address of this lane's point i (walls: its physical point)
     auto addr = [&](int i) -> int64_t {
         if constexpr (EXT == 0) return base + i * step;
         else return base + (int64_t)ext_index<EXT, N>(i * N2 + t) * A.S;
@@ -329,12 +338,12 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
         if (act)
             sfor<0, N1>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                if (EXT == 0 || i * N2 + t < NP) X[addr(i)] = a[i];
+                X[addr(i)] = ext_sign<EXT, N, T>(i * N2 + t) * a[i];
             });
     };
     // one array: diffuse, [capture], [multiply by e2 = E4^2, diffuse again]
     auto run_on = [&](cx<T>* X, cx<T>(&a)[N1], const SOps<T>& op, const cx<T>(&e2)[N1], bool have_e2) {
-        diffuse<N1, N2>(a, t, sh, lay, op.g1);
+        line_diffuse<EXT, N1, N2>(a, t, sh, lay, op.g1);
         if (op.acap) stX(op.acap, a);
         if (AXIS == 0 && op.e) {  // field multiplies happen only in the x pass
             if (have_e2) {
@@ -342,11 +351,11 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
             } else if (act) {
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
-                    const cx<T> e = op.e[addr(i)];  // field tables: even images
+                    const cx<T> e = op.e[addr(i)];  // field tables: no sign
                     a[i] = a[i] * (e * e);
                 });
             }
-            if (op.g2) diffuse<N1, N2>(a, t, sh, lay, op.g2);
+            if (op.g2) line_diffuse<EXT, N1, N2>(a, t, sh, lay, op.g2);
         }
         stX(X, a);
     };
@@ -368,7 +377,7 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
         return;
     }
     if (AXIS == 0 && A.opU.g1 && A.opV.g1 && A.opU.e && A.opU.e == A.opV.e) {
-        // both arrays take the same field table: read it once (even image)
+        // both arrays take the same field table: read it once
         if (act) {
             sfor<0, N1>([&](auto I) { e2[decltype(I)::value] = A.opU.e[addr(decltype(I)::value)]; });
         } else {
@@ -391,7 +400,7 @@ __global__ __launch_bounds__((SShape<T, N2, W>::kThreads), MW) void k_spass(SArg
     spass_body<T, N1, N2, AXIS, W>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
-// Walled x or y lines: the mirror image of NP = N1 N2 / 2 physical points.
+// Walled x or y lines of N1 N2 points.
 template <typename T, int N1, int N2, int AXIS, int EXT>
 __global__ __launch_bounds__((SShape<T, N2, 1>::kThreads)) void k_spass_walls(SArgs<T> A)
 {
@@ -510,9 +519,9 @@ PFT_DECLARE_LAUNCHERS(v0)
 PFT_DECLARE_LAUNCHERS(alt)
 #undef PFT_DECLARE_LAUNCHERS
 
-// Walled passes (EXT = 1 reflecting, 2 absorbing) over lines of n physical
-// points: the kernels of axis length 2n run on the mirror images.  Defined
-// for n with 2n in the axis list.
+// Walled passes (EXT = 1 reflecting, 2 absorbing) over lines of n points,
+// for every n of the axis list (default radix split), with the factor tables
+// of pair_diffuse().
 template <typename T>
 hipError_t launch_zpass_walls(int nz, int ext, const ZArgs<T>& a, hipStream_t s);
 template <typename T>

@@ -8,7 +8,7 @@ bool walls_supported(int n)
 {
 #define PFT_CASE(NP, N1, N2) \
     if (n == NP) return true;
-    PFT_WALL_SIZES(PFT_CASE)
+    PFT_AXIS_SIZES(PFT_CASE)
 #undef PFT_CASE
     return false;
 }

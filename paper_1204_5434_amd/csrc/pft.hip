@@ -29,6 +29,7 @@ thread_local LaunchEvents g_launch_events;
 namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.1415926535897932384626433832795;
 
 // ============================================================ device code ==
 
@@ -973,7 +974,7 @@ struct Work {
     hipStream_t stream = nullptr;  // NULL: the context's stream
 };
 
-// The z pass on the context's grid: the mirror-image kernels on a walled z axis.
+// The z pass on the context's grid (the walled kernels on a walled z axis).
 template <typename T>
 hipError_t launch_z(const pft_ctx* c, const pft::ZArgs<T>& a, hipStream_t st)
 {
@@ -1443,6 +1444,36 @@ std::vector<T> axis_factors(int n, double L, double h)
     return g;
 }
 
+// Tables of the walled line diffusion (pair_diffuse): for each frequency m of
+// the reordered line, alpha_m = (g_m + g_{n-m}) / 2 and
+// beta_m = (g_m - g_{n-m}) exp(i pi m / n) / 2, with g_m = exp(-(pi m / L)^2 h)
+// for the cosine modes of reflecting walls and g_m = exp(-(pi (n - m) / L)^2 h)
+// for the sine modes of absorbing walls (alpha_0 = g_0, beta_0 = 0), all / n.
+template <typename T>
+std::vector<T> wall_factors(int n, double L, double h, int bc)
+{
+    auto g = [&](int m) {
+        const double mode = bc == PFT_ABSORBING ? (double)(n - m) : (double)m;
+        const double k = kPi * mode / L;
+        return std::exp(-k * k * h) / n;
+    };
+    std::vector<T> ab(3 * (size_t)n);
+    for (int m = 0; m < n; ++m) {
+        double al = g(m), br = 0.0, bi = 0.0;
+        if (m > 0) {
+            const double gp = g(m), gq = g(n - m);
+            al = 0.5 * (gp + gq);
+            const double d = 0.5 * (gp - gq), th = kPi * m / n;
+            br = d * std::cos(th);
+            bi = d * std::sin(th);
+        }
+        ab[3 * m] = T(al);
+        ab[3 * m + 1] = T(br);
+        ab[3 * m + 2] = T(bi);
+    }
+    return ab;
+}
+
 template <typename T>
 pft_status upload_factors(pft_ctx* c, int hid, double h)
 {
@@ -1450,9 +1481,9 @@ pft_status upload_factors(pft_ctx* c, int hid, double h)
     const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
     for (int full = 0; full < 2; ++full)
         for (int ax = 0; ax < 3; ++ax) {
-            // a walled axis diffuses the 2n-point mirror image with period 2L
-            const int w = c->p.bc[ax] ? 2 : 1;
-            const std::vector<T> g = axis_factors<T>(w * n[ax], w * L[ax], full ? h : h / 2);
+            const double hh = full ? h : h / 2;
+            const std::vector<T> g = c->p.bc[ax] ? wall_factors<T>(n[ax], L[ax], hh, c->p.bc[ax])
+                                                 : axis_factors<T>(n[ax], L[ax], hh);
             PFT_HIP(c, hipMemcpy(const_cast<T*>(gptr<T>(c, hid, full, ax)), g.data(), g.size() * sizeof(T),
                                  hipMemcpyHostToDevice));
         }
@@ -2437,7 +2468,8 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
     c->fused = fused_default(p);
     c->stream = static_cast<hipStream_t>(hip_stream);
     c->M = (int64_t)p.nx * p.ny * p.nz;
-    c->maxN = std::max((p.bc[0] ? 2 : 1) * p.nx, std::max((p.bc[1] ? 2 : 1) * p.ny, (p.bc[2] ? 2 : 1) * p.nz));
+    // table slot length: n factors per periodic axis, 3n per walled axis
+    c->maxN = std::max((p.bc[0] ? 3 : 1) * p.nx, std::max((p.bc[1] ? 3 : 1) * p.ny, (p.bc[2] ? 3 : 1) * p.nz));
     c->elem = p.precision == PFT_C128 ? sizeof(cx<double>) : sizeof(cx<float>);
     c->h.resize(p.ns + 1);
     c->blk.resize(p.ns + 1);

@@ -1,9 +1,10 @@
 """GPU parity with walls (pft_params.bc: reflecting = cosine modes, absorbing =
 sine modes, per axis) against the oracle's walled diffusion, which is written
-from the transform definitions (the GPU runs periodic kernels on mirror
-images).  Covers every walled line-length class (one lane per line up to
-sixteen lanes), both schemes, both precisions, the fused yz schedule with a
-walled x axis, and the calls that need a periodic box."""
+from the transform definitions (the GPU uses one N-point transform of the
+reordered line with paired frequencies).  Covers every line-length class
+(one lane per line up to sixteen lanes), both schemes, both precisions, the
+fused yz schedule with a walled x axis, and the calls that need a periodic
+box."""
 import numpy as np
 import pytest
 import torch
@@ -42,6 +43,9 @@ DIFFUSE = [
     ((64, 8, 16), (8.0, 1.0, 2.0), (2, 0, 0)),
     ((12, 96, 8), (1.5, 12.0, 1.0), (0, 1, 0)),
     ((8, 8, 128), (1.0, 1.0, 16.0), (0, 0, 2)),
+    ((80, 12, 20), (10.0, 1.5, 2.5), (1, 2, 1)),
+    ((16, 192, 8), (2.0, 24.0, 1.0), (0, 2, 1)),
+    ((8, 12, 256), (1.0, 1.5, 32.0), (0, 0, 1)),
 ]
 
 
@@ -108,7 +112,7 @@ def test_walled_rejections():
     with pytest.raises(B.PftError) as e:
         B.Batch([p])
     assert e.value.status == B.PFT_E_UNSUPPORTED
-    for bad, status in (((80, 16, 16), B.PFT_E_UNSUPPORTED), ((192, 16, 16), B.PFT_E_UNSUPPORTED)):
+    for bad, status in (((36, 16, 16), B.PFT_E_UNSUPPORTED), ((160, 16, 16), B.PFT_E_UNSUPPORTED)):
         with pytest.raises(B.PftError) as e:
             B.Context(gparams(bad, (4.0,) * 3, 10, 0.5, B.PFT_C128, (2, 0, 0)))
         assert e.value.status == status
