@@ -47,6 +47,9 @@ CASES = [
     ((12, 16, 8), (3.0, 4.0, 2.0), 25, 0.3, 18.0, 1.0, 0),   # junction inside a step
     ((8, 12, 16), (2.0, 3.0, 4.0), 13, 0.62, 12.0, 1.0, 1),  # plain split + junction
     ((24, 8, 12), (6.0, 2.0, 3.0), 10, 0.4, 14.4, 3.0, 1),
+    ((8, 8, 8), (2.0, 2.0, 2.0), 2, 0.5, 15.0, 1.0, 0),       # shortest contour
+    ((12, 8, 16), (3.0, 2.0, 4.0), 10, 0.03, 15.0, 1.0, 0),   # junction inside the first step
+    ((8, 12, 12), (2.0, 3.0, 3.0), 10, 0.97, 15.0, 2.0, 1),   # junction inside the last step
 ]
 
 

@@ -166,6 +166,11 @@ CASES = [
     ((128, 8, 8), (16.0, 1.0, 1.0), 10, 0.45, 20.0, 1.0, 0),
     ((8, 8, 256), (1.0, 1.0, 32.0), 8, 0.5, 20.0, 1.0, 0),
     ((8, 192, 8), (1.0, 24.0, 1.0), 9, 0.55, 20.0, 1.0, 1),
+    # degenerate contours
+    ((8, 8, 8), (2.0, 2.0, 2.0), 2, 0.5, 15.0, 1.0, 0),       # shortest: one A and one B step
+    ((16, 12, 8), (4.0, 3.0, 2.0), 10, 0.03, 15.0, 1.0, 0),   # junction inside the first step
+    ((12, 16, 8), (3.0, 4.0, 2.0), 10, 0.97, 15.0, 1.0, 1),   # junction inside the last step
+    ((8, 16, 12), (2.0, 4.0, 3.0), 9, 1.0 / 9.0, 15.0, 1.0, 0),  # a single A step
 ]
 
 
