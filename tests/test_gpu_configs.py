@@ -7,7 +7,9 @@ follow and through exact properties where it cannot:
 * 256^3, Ns = 200, complex64 propagators (~54 GB of stored q and q-dagger):
   sampled one-step parity of stored slices, per-node Q and total density, a
   Langevin step, and a checkpointed FP32 gradient pass checked against the
-  density force and the FP64 reverse mode of the same state.
+  density force and the FP64 reverse mode of the same state;
+* the same 256^3 workload with complex128 stores (~108 GB): sampled one-step
+  parity, per-node Q and total density.
 """
 import numpy as np
 import pytest
@@ -156,3 +158,34 @@ def test_cl256_large_single_gpu(orc):
     for ax in range(3):
         assert abs(complex(dL[ax]) - complex(dL64[ax])) <= 2e-5 * (abs(complex(dL64[ax])) + w.C * V / w.L[ax])
     c64.close()
+
+
+def test_cl256_complex128_largest_stores(orc):
+    """The 256^3, Ns = 200 workload with both stores in complex128 (~108 GB of
+    HBM): sampled one-step parity of stored slices against the oracle's step,
+    per-node Q and total density at full size."""
+    w = inputs.CL256
+    say("cl256: complex128 stores of", 2 * 201 * w.M * 16 / 1e9, "GB")
+    wp, wm = inputs.fields(w)
+    ctx = B.Context(B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, B.PFT_C128, B.PFT_RQM4))
+    out = ctx.evaluate(dev(wp), dev(wm))
+    K = ctx.K
+    p = op(orc, w)
+    wA, wB = orc.block_fields(p, wp, wm)
+    h, blk, J = orc.contour(w.ns, w.f)
+    qj = torch.empty(w.n, dtype=torch.complex128, device=DEV)
+    qj1 = torch.empty_like(qj)
+    for which, j in ((0, K // 2), (1, K - 1)):
+        say("cl256 complex128 one-step check", which, j)
+        ctx.pft_get_slice(which, j, qj)
+        ctx.pft_get_slice(which, j + 1, qj1)
+        si = j if which == 0 else K - 1 - j
+        ref = orc.step(p, h[si], wA if blk[si] == 0 else wB, host(qj))
+        assert np.abs(host(qj1) - ref).max() <= 1e-12 * np.abs(ref).max()
+    qn = torch.empty(K + 1, dtype=torch.complex128, device=DEV)
+    ctx.pft_node_q(qn)
+    Qv = host(out["Q"])[0]
+    assert np.abs(host(qn) - Qv).max() <= 1e-11 * abs(Qv)
+    assert abs(host(out["phiA"] + out["phiB"]).sum() - w.M) <= 1e-10 * w.M
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
