@@ -354,8 +354,15 @@ def debye(x: float) -> float:
     return lib().or_debye(float(x))
 
 
+def _sis_walls_ok(p: Params):
+    if any(b == 2 for b in p.bc):
+        raise ValueError("the semi-implicit step has no diagonal linear response between absorbing walls")
+
+
 def sis_update(p: Params, wp, wm, phiA, phiB, dt, lam_p=1.0, lam_m=1.0, noise=False, seed=0, replica=0, step_=0):
-    """Return the updated (w_+, w_-) after one semi-implicit step (Eq. (10))."""
+    """Return the updated (w_+, w_-) after one semi-implicit step (Eq. (10));
+    periodic axes filter in the Fourier basis, reflecting ones in the cosine basis."""
+    _sis_walls_ok(p)
     wp = np.array(wp, dtype=np.complex128, order="C", copy=True)
     wm = np.array(wm, dtype=np.complex128, order="C", copy=True)
     phiA, phiB = _cfield(phiA, p.shape), _cfield(phiB, p.shape)
@@ -365,6 +372,7 @@ def sis_update(p: Params, wp, wm, phiA, phiB, dt, lam_p=1.0, lam_m=1.0, noise=Fa
 
 
 def edwards_sis_update(p: Params, B: float, omega, phi, dt, lam=1.0, noise=False, seed=0, replica=0, step_=0):
+    _sis_walls_ok(p)
     omega = np.array(omega, dtype=np.complex128, order="C", copy=True)
     phi = _cfield(phi, p.shape)
     lib().or_edwards_sis_update(ctypes.byref(p._c()), B, _ptr(omega), _ptr(phi), dt, lam, int(bool(noise)),

@@ -678,9 +678,90 @@ double or_debye(double x)
     return 2.0 * (exp(-x) + x - 1.0) / (x * x);
 }
 
+/* Cosine transform along one reflecting axis, in place, as the definitions
+ * (the DCT-II / DCT-III pair of the walled diffusion above):
+ *   forward  X_m = sum_n u_n cos(pi m (n+1/2)/N),
+ *   inverse  u_n = X_0 / N + (2/N) sum_{m>=1} X_m cos(pi m (n+1/2)/N). */
+static void dct_axis(const or_params *p, cplx *u, int axis, int inverse)
+{
+    const int n = (axis == 0) ? p->nx : (axis == 1) ? p->ny : p->nz;
+    const ptrdiff_t stride = (axis == 0) ? (ptrdiff_t)p->ny * p->nz : (axis == 1) ? p->nz : 1;
+    const int64_t nlines = grid_m(p) / n;
+    const double pi = OR_TWO_PI / 2.0;
+    #pragma omp parallel
+    {
+        cplx *in = (cplx *)malloc(sizeof(cplx) * n);
+        #pragma omp for schedule(static)
+        for (int64_t l = 0; l < nlines; l++) {
+            ptrdiff_t base;
+            if (axis == 2) base = l * p->nz;
+            else if (axis == 1) base = (l / p->nz) * (ptrdiff_t)p->ny * p->nz + (l % p->nz);
+            else base = l;
+            for (int i = 0; i < n; i++) in[i] = u[base + i * stride];
+            for (int o = 0; o < n; o++) {
+                cplx acc = 0.0;
+                if (!inverse) {
+                    for (int i = 0; i < n; i++) acc += in[i] * cos(pi * o * (i + 0.5) / n);
+                } else {
+                    acc = in[0];
+                    for (int m = 1; m < n; m++) acc += 2.0 * in[m] * cos(pi * m * (o + 0.5) / n);
+                    acc /= (double)n;
+                }
+                u[base + o * stride] = acc;
+            }
+        }
+        free(in);
+    }
+}
+
+/* u <- u - T^-1[ T(r) / (1 + a g(k)) ] with g(k) = g0 + gD * g_D(|k|^2): T is
+ * the 3-D DFT in a periodic box; with reflecting walls (Sec. III) it is the
+ * cosine transform along the walled axes (k = pi m / L there, m = 0..N-1)
+ * and the DFT along the others (k = 2 pi m / L).  Absorbing walls have no
+ * diagonal linear response and are not handled here. */
+static void sis_apply_walls(const or_params *p, cplx *u, const cplx *r, double a, double g0, double gD)
+{
+    const int64_t M = grid_m(p);
+    const int32_t n[3] = {p->nx, p->ny, p->nz};
+    const double L[3] = {p->lx, p->ly, p->lz};
+    cplx *t = (cplx *)malloc(sizeof(cplx) * M);
+    memcpy(t, r, sizeof(cplx) * M);
+    for (int axis = 0; axis < 3; axis++) {
+        if (p->bc[axis]) dct_axis(p, t, axis, 0);
+        else fft_axis(t, p->nx, p->ny, p->nz, axis, -1);
+    }
+    for (int64_t jx = 0; jx < p->nx; jx++)
+        for (int64_t jy = 0; jy < p->ny; jy++)
+            for (int64_t jz = 0; jz < p->nz; jz++) {
+                const int64_t j[3] = {jx, jy, jz};
+                double k2 = 0.0;
+                for (int axis = 0; axis < 3; axis++) {
+                    const double k = p->bc[axis] ? (OR_TWO_PI / 2.0) * j[axis] / L[axis]
+                                                 : OR_TWO_PI * or_mode((int32_t)j[axis], n[axis]) / L[axis];
+                    k2 += k * k;
+                }
+                const int64_t x = (jx * p->ny + jy) * p->nz + jz;
+                t[x] = t[x] / (1.0 + a * (g0 + gD * or_debye(k2)));
+            }
+    for (int axis = 0; axis < 3; axis++) {
+        if (p->bc[axis]) {
+            dct_axis(p, t, axis, 1);
+        } else {
+            fft_axis(t, p->nx, p->ny, p->nz, axis, +1);
+            for (int64_t x = 0; x < M; x++) t[x] /= (double)n[axis];
+        }
+    }
+    for (int64_t x = 0; x < M; x++) u[x] -= t[x];
+    free(t);
+}
+
 /* u <- u - IDFT[ DFT(r) / (1 + a g(k)) ] with g(k) = g0 + gD * g_D(|k|^2). */
 static void sis_apply(const or_params *p, cplx *u, const cplx *r, double a, double g0, double gD)
 {
+    if (p->bc[0] || p->bc[1] || p->bc[2]) {
+        sis_apply_walls(p, u, r, a, g0, gD);
+        return;
+    }
     const int64_t M = grid_m(p);
     cplx *t = (cplx *)malloc(sizeof(cplx) * M);
     memcpy(t, r, sizeof(cplx) * M);
