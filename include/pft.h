@@ -84,9 +84,10 @@ typedef struct {
  * N points is diffused with one N-point transform of its even/odd-reordered
  * points and a pairing of frequencies m and N - m, for every N of the axis
  * list (else PFT_E_UNSUPPORTED).  Walled contexts run the axis
- * schedule on walled y or z axes, and pft_adjoint, pft_debug_kgrid, the
- * semi-implicit step and batches accept periodic boxes only
- * (PFT_E_UNSUPPORTED). */
+ * schedule on walled y or z axes; the semi-implicit step takes reflecting
+ * walls (modes of the cosine basis) when 2N is in the axis list, not
+ * absorbing ones; pft_adjoint, pft_debug_kgrid and batches accept periodic
+ * boxes only (PFT_E_UNSUPPORTED). */
 typedef enum { PFT_PERIODIC = 0, PFT_REFLECTING = 1, PFT_ABSORBING = 2 } pft_boundary;
 
 /* Where the propagators live (diblock model).
@@ -132,8 +133,10 @@ typedef struct {
                         g = g_D(|k|^2) (Debye function of the whole chain,
                         lengths in R_g) for w_+, g = 2/chiN for w_- (its
                         explicitly linear term; local in real space), and
-                        g = B/C + g_D(|k|^2) for the Edwards field.  Batches
-                        accept 0 only. */
+                        g = B/C + g_D(|k|^2) for the Edwards field; between
+                        reflecting walls the modes of a walled axis are the
+                        cosine modes, k = pi m / L (the filter runs on the
+                        even image of period 2L).  Batches accept 0 only. */
 } pft_step;
 
 /* Create a context for one parameter set on the current HIP device.

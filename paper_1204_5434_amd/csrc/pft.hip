@@ -484,6 +484,43 @@ __global__ void k_sis_increment(SisIncArgs a)
     }
 }
 
+// Between reflecting walls the filter runs on the even mirror image of the
+// increment, of period 2L along each walled axis (ne = 2n there), where the
+// Fourier basis is the cosine basis of the walled box: X = image of R, W = 0.
+struct MirrorArgs {
+    const double2* R;
+    double2* X;
+    double2* W;
+    int n[3], ne[3];
+    int64_t Me;
+};
+
+__global__ void k_sis_mirror(MirrorArgs a)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.Me; e += (int64_t)gridDim.x * blockDim.x) {
+        const int ze = (int)(e % a.ne[2]);
+        const int ye = (int)((e / a.ne[2]) % a.ne[1]);
+        const int xe = (int)(e / ((int64_t)a.ne[1] * a.ne[2]));
+        const int x = xe < a.n[0] ? xe : 2 * a.n[0] - 1 - xe;
+        const int y = ye < a.n[1] ? ye : 2 * a.n[1] - 1 - ye;
+        const int z = ze < a.n[2] ? ze : 2 * a.n[2] - 1 - ze;
+        a.X[e] = a.R[((int64_t)x * a.n[1] + y) * a.n[2] + z];
+        a.W[e] = make_double2(0.0, 0.0);
+    }
+}
+
+// w += W on the physical part of the image (W holds minus the filtered increment).
+__global__ void k_sis_unmirror(MirrorArgs a, double2* __restrict__ w, int64_t M)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+        const int z = (int)(i % a.n[2]);
+        const int y = (int)((i / a.n[2]) % a.n[1]);
+        const int x = (int)(i / ((int64_t)a.n[1] * a.n[2]));
+        const double2 d = a.W[((int64_t)x * a.ne[1] + y) * a.ne[2] + z];
+        w[i] = make_double2(w[i].x + d.x, w[i].y + d.y);
+    }
+}
+
 // ------------------------------------------------------------ reverse mode --
 // Per-step contribution to dQ/dw_b (times M) of step j, accumulated in FP64
 // with Neumaier compensation into the block's (sum, comp) arrays.  With
@@ -845,6 +882,7 @@ struct pft_ctx {
     hipStream_t cs = nullptr;     // copy stream
     hipEvent_t ev_st[kRing] = {}, ev_cp[kRing] = {}, ev_rd[kRing] = {}, ev_fr[kRing] = {}, ev_done = nullptr;
     double2* sisbuf = nullptr;    // semi-implicit step: the filtered increment (M)
+    double2* sisext = nullptr;    // ... between reflecting walls: its even image and the result (2 Me)
     double2* partials = nullptr;  // reduction scratch
     double2* scal = nullptr;      // [0] Q, [1] H, [2] h, [3..] node Q
     uint32_t* flags = nullptr;
@@ -1897,7 +1935,7 @@ void free_all(pft_ctx* c)
     c->qh = nullptr;
     void* bufs[] = {c->qs,  c->qds,  c->U,        c->V,    c->U2,    c->V2,  c->E,   c->work,
                     c->gtab, c->tau, c->phi,      c->partials, c->scal, c->flags, c->adj, c->adjG,
-                    c->adjAcc, c->k2, c->sisbuf, c->ring};
+                    c->adjAcc, c->k2, c->sisbuf, c->sisext, c->ring};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
@@ -2679,14 +2717,26 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
             return c->fail(PFT_E_NOMEM, "semi-implicit step: cannot allocate the work array");
         }
     }
+    // reflecting walls: the filter runs on the even image (2n points, period 2L)
+    const bool walls = p.bc[0] || p.bc[1] || p.bc[2];
+    const int n[3] = {p.nx, p.ny, p.nz};
+    int ne[3];
+    for (int ax = 0; ax < 3; ++ax) ne[ax] = p.bc[ax] ? 2 * n[ax] : n[ax];
+    const int64_t Me = (int64_t)ne[0] * ne[1] * ne[2];
+    if (walls && !c->sisext) {
+        if (hipMalloc((void**)&c->sisext, 2 * (size_t)Me * sizeof(double2)) != hipSuccess) {
+            (void)hipGetLastError();
+            c->sisext = nullptr;
+            return c->fail(PFT_E_NOMEM, "semi-implicit step: cannot allocate the mirror image");
+        }
+    }
     if (!c->k2) {
         std::vector<double> k2(3 * (size_t)c->maxN, 0.0);
-        const int n[3] = {p.nx, p.ny, p.nz};
         const double L[3] = {p.lx, p.ly, p.lz};
         for (int ax = 0; ax < 3; ++ax)
-            for (int j = 0; j < n[ax]; ++j) {
-                const int m = (j <= n[ax] / 2) ? j : j - n[ax];
-                const double k = kTwoPi * m / L[ax];
+            for (int j = 0; j < ne[ax]; ++j) {
+                const int m = (j <= ne[ax] / 2) ? j : j - ne[ax];
+                const double k = kTwoPi * m / ((double)ne[ax] / n[ax] * L[ax]);
                 k2[(size_t)ax * c->maxN + j] = k * k;
             }
         if (hipMalloc((void**)&c->k2, k2.size() * sizeof(double)) != hipSuccess) {
@@ -2720,20 +2770,37 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
         hipLaunchKernelGGL(k_sis_increment, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
     }
     PFT_HIP(c, hipGetLastError());
+    MirrorArgs ma{};
+    if (walls) {
+        ma.R = c->sisbuf;
+        ma.X = c->sisext;
+        ma.W = c->sisext + Me;
+        for (int ax = 0; ax < 3; ++ax) {
+            ma.n[ax] = n[ax];
+            ma.ne[ax] = ne[ax];
+        }
+        ma.Me = Me;
+        hipLaunchKernelGGL(k_sis_mirror, dim3(grid_for(Me, 256)), dim3(256), 0, c->stream, ma);
+        PFT_HIP(c, hipGetLastError());
+    }
     pft::SisArgs f{};
-    f.X = reinterpret_cast<cx<double>*>(c->sisbuf);
-    f.W = reinterpret_cast<cx<double>*>(u.wp);
+    f.X = reinterpret_cast<cx<double>*>(walls ? ma.X : c->sisbuf);
+    f.W = reinterpret_cast<cx<double>*>(walls ? ma.W : u.wp);
     f.k2x = c->k2;
     f.k2y = c->k2 + c->maxN;
     f.k2z = c->k2 + 2 * (size_t)c->maxN;
-    f.nz = p.nz;
+    f.nz = ne[2];
     f.a = u.dtp;
     f.g0 = u.edwards ? u.b_over_c : 0.0;
     f.gD = 1.0;
-    f.inv_M = 1.0 / (double)c->M;
+    f.inv_M = 1.0 / (double)Me;
     for (int kind = 0; kind < 5; ++kind) {
-        ProfScope ps(c, PFT_K_REDUCE, (kind == 4 ? 3.0 : 2.0) * sizeof(double2) * (double)c->M);
-        PFT_HIP(c, pft::launch_sis_pass(kind, p.nx, p.ny, p.nz, f, c->stream));
+        ProfScope ps(c, PFT_K_REDUCE, (kind == 4 ? 3.0 : 2.0) * sizeof(double2) * (double)Me);
+        PFT_HIP(c, pft::launch_sis_pass(kind, ne[0], ne[1], ne[2], f, c->stream));
+    }
+    if (walls) {
+        hipLaunchKernelGGL(k_sis_unmirror, dim3(grid_for(c->M, 256)), dim3(256), 0, c->stream, ma, u.wp, c->M);
+        PFT_HIP(c, hipGetLastError());
     }
     return PFT_OK;
 }
@@ -2746,8 +2813,16 @@ pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, d
     if (!(st->dt >= 0) || !(st->lambda_plus >= 0) || !(st->lambda_minus >= 0))
         return c->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
     if (st->update != 0 && st->update != 1) return c->fail(PFT_E_INVALID, "update must be 0 or 1");
-    if (st->update == 1 && (c->p.bc[0] || c->p.bc[1] || c->p.bc[2]))
-        return c->fail(PFT_E_UNSUPPORTED, "the semi-implicit step needs a periodic box");
+    if (st->update == 1)
+        for (int ax = 0; ax < 3; ++ax) {
+            const int nn = ax == 0 ? c->p.nx : ax == 1 ? c->p.ny : c->p.nz;
+            int n1, n2, w;
+            if (c->p.bc[ax] == PFT_ABSORBING)
+                return c->fail(PFT_E_UNSUPPORTED, "the semi-implicit step has no linear response between absorbing walls");
+            if (c->p.bc[ax] == PFT_REFLECTING && !pft::axis_variant(2 * nn, 0, &n1, &n2, &w))
+                return c->fail(PFT_E_UNSUPPORTED, "semi-implicit step between walls: no kernel for the image length %d",
+                               2 * nn);
+        }
     if ((phi_a && !aligned16(phi_a)) || (phi_b && !aligned16(phi_b)) || (Q && !aligned16(Q)) || (H && !aligned16(H)))
         return c->fail(PFT_E_INVALID, "optional outputs must be 16-byte aligned");
     double* pa = phi_a ? phi_a : reinterpret_cast<double*>(c->phi);

@@ -105,17 +105,73 @@ def test_walled_rejections():
     with pytest.raises(B.PftError) as e:
         ctx.pft_adjoint(t, t, t.clone(), t.clone())
     assert e.value.status == B.PFT_E_UNSUPPORTED
-    with pytest.raises(B.PftError) as e:
-        ctx.pft_cl_step(t.clone(), t.clone(), B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1))
-    assert e.value.status == B.PFT_E_UNSUPPORTED
     ctx.close()
+    # the semi-implicit step: no linear response between absorbing walls, and
+    # reflecting walls need a kernel for the image length 2n
+    for bc, n in (((0, 2, 0), (16, 16, 16)), ((1, 0, 0), (80, 8, 8))):
+        ctx = B.Context(gparams(n, (4.0,) * 3, 10, 0.5, B.PFT_C128, bc))
+        t = torch.zeros(n, dtype=torch.complex128, device=DEV)
+        with pytest.raises(B.PftError) as e:
+            ctx.pft_cl_step(t.clone(), t.clone(), B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1))
+        assert e.value.status == B.PFT_E_UNSUPPORTED
+        ctx.close()
     with pytest.raises(B.PftError) as e:
         B.Batch([p])
     assert e.value.status == B.PFT_E_UNSUPPORTED
-    for bad, status in (((36, 16, 16), B.PFT_E_UNSUPPORTED), ((160, 16, 16), B.PFT_E_UNSUPPORTED)):
+    for bad, status in (((36, 16, 16), B.PFT_E_UNSUPPORTED), ((176, 16, 16), B.PFT_E_UNSUPPORTED)):
         with pytest.raises(B.PftError) as e:
             B.Context(gparams(bad, (4.0,) * 3, 10, 0.5, B.PFT_C128, (2, 0, 0)))
         assert e.value.status == status
     with pytest.raises(B.PftError) as e:
         B.Context(gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (3, 0, 0)))
     assert e.value.status == B.PFT_E_INVALID
+
+
+SIS_WALLS = [
+    # n, L, bc
+    ((16, 12, 20), (2.0, 1.5, 2.5), (1, 0, 1)),
+    ((24, 32, 8), (3.0, 4.0, 1.0), (0, 1, 0)),
+    ((12, 16, 24), (1.5, 2.0, 3.0), (1, 1, 1)),
+]
+
+
+@pytest.mark.parametrize("n,L,bc", SIS_WALLS, ids=[f"{c[0]}-{c[2]}" for c in SIS_WALLS])
+@pytest.mark.parametrize("noise", [0, 1])
+def test_semi_implicit_step_between_reflecting_walls(orc, n, L, bc, noise):
+    say("semi-implicit step with walls", n, bc, noise)
+    r = np.random.default_rng(50 + sum(n))
+    wp = 0.3 * r.standard_normal(n) + 0.05j * r.standard_normal(n)
+    wm = 0.4 * r.standard_normal(n) + 0.05j * r.standard_normal(n)
+    ns, f = 10, 0.4
+    p_or = oparams(orc, n, L, ns, f, bc)
+    ctx = B.Context(gparams(n, L, ns, f, B.PFT_C128, bc))
+    gwp, gwm = dev(wp), dev(wm)
+    pa = torch.empty(n, dtype=torch.complex128, device=DEV)
+    pb = torch.empty_like(pa)
+    ctx.pft_cl_step(gwp, gwm, B.pft_step(0.6, 1.0, 0.7, 7, 1, 2, noise, 1), pa, pb)
+    np_, nm_ = orc.sis_update(p_or, wp, wm, host(pa), host(pb), 0.6, 1.0, 0.7, noise=bool(noise), seed=7,
+                              replica=1, step_=2)
+    scale = max(np.abs(np_).max(), np.abs(nm_).max())
+    assert np.abs(host(gwp) - np_).max() <= 1e-12 * scale
+    assert np.abs(host(gwm) - nm_).max() <= 1e-12 * scale
+    ref = orc.evaluate(p_or, wp, wm)
+    ep, em = orc.sis_update(p_or, wp, wm, ref["phiA"], ref["phiB"], 0.6, 1.0, 0.7, noise=bool(noise), seed=7,
+                            replica=1, step_=2)
+    assert np.abs(host(gwp) - ep).max() <= 1e-10 * scale
+    assert np.abs(host(gwm) - em).max() <= 1e-10 * scale
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
+
+
+def test_semi_implicit_edwards_step_between_reflecting_walls(orc):
+    n, L, bc, ns, C, Bv = (16, 16, 16), (2.0, 2.0, 2.0), (1, 1, 1), 12, 3.0, 1.5
+    r = np.random.default_rng(57)
+    om = 0.3 * r.standard_normal(n) + 0.05j * r.standard_normal(n)
+    p_or = orc.Params(*n, *L, ns, 0.5, 1.0, C, 0, False, bc)
+    ctx = B.Context(B.Params(*n, *L, ns, 0.5, 1.0, C, B.PFT_C128, B.PFT_RQM4, B.PFT_EDWARDS, Bv, B.PFT_STORE_BOTH, bc))
+    g = dev(om)
+    phi = torch.empty(n, dtype=torch.complex128, device=DEV)
+    ctx.pft_cl_step(g, None, B.pft_step(0.5, 1.2, 1.0, 4, 0, 1, 1, 1), phi)
+    filt = orc.edwards_sis_update(p_or, Bv, om, host(phi), 0.5, 1.2, noise=True, seed=4, replica=0, step_=1)
+    assert np.abs(host(g) - filt).max() <= 1e-12 * np.abs(filt).max()
+    ctx.close()
