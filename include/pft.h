@@ -86,8 +86,9 @@ typedef struct {
  * list (else PFT_E_UNSUPPORTED).  Walled contexts run the axis
  * schedule on walled y or z axes; the semi-implicit step takes reflecting
  * walls (modes of the cosine basis) when 2N is in the axis list, not
- * absorbing ones; pft_adjoint, pft_debug_kgrid and batches accept periodic
- * boxes only (PFT_E_UNSUPPORTED). */
+ * absorbing ones; pft_adjoint gives dH/dw with walls but dH/dL for periodic
+ * boxes only; pft_debug_kgrid and batches accept periodic boxes only
+ * (PFT_E_UNSUPPORTED). */
 typedef enum { PFT_PERIODIC = 0, PFT_REFLECTING = 1, PFT_ABSORBING = 2 } pft_boundary;
 
 /* Where the propagators live (diblock model).
@@ -252,7 +253,9 @@ pft_status pft_cl_step(pft_ctx* ctx, double* w_plus, double* w_minus, const pft_
  * dH_dL -- 3 complex128 (may be NULL): dH/dL_x, dH/dL_y, dH/dL_z with each box
  * edge varied alone and the field values on the grid held fixed (the diagonal
  * box stress times the volume over the edge); H -- complex128 (may be NULL),
- * the Hamiltonian of these fields.  Overwrites the context's field tables and
+ * the Hamiltonian of these fields.  With walls the field derivatives hold (the
+ * walled diffusion is symmetric too) and dH_dL must be NULL.  Overwrites the
+ * context's field tables and
  * Q, so pft_densities / pft_hamiltonian need a new pft_propagate afterwards.
  * Errors: PFT_E_INVALID, PFT_E_NOMEM, PFT_E_DEVICE. */
 pft_status pft_adjoint(pft_ctx* ctx, const double* w_plus, const double* w_minus, int32_t ckpt_every,

@@ -2930,7 +2930,8 @@ pft_status pft_adjoint(pft_ctx* c, const double* wp, const double* wm, int32_t c
     if (ckpt_every < 0) return c->fail(PFT_E_INVALID, "pft_adjoint: ckpt_every must be >= 0");
     if (c->p.model != PFT_DIBLOCK) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: diblock model only");
     if (c->p.storage != PFT_STORE_BOTH) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: needs both stores");
-    if (c->p.bc[0] || c->p.bc[1] || c->p.bc[2]) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: periodic box only");
+    if (dL && (c->p.bc[0] || c->p.bc[1] || c->p.bc[2]))
+        return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: the box derivative needs a periodic box (pass dH_dL = NULL)");
     int Kc = ckpt_every;
     if (Kc == 0) Kc = (int)std::ceil(std::sqrt((double)c->K));
     Kc = std::max(1, std::min(Kc, c->K));

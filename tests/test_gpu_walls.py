@@ -102,8 +102,9 @@ def test_walled_rejections():
     p = gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (1, 0, 0))
     ctx = B.Context(p)
     t = torch.zeros((16, 16, 16), dtype=torch.complex128, device=DEV)
+    dL = torch.empty(3, dtype=torch.complex128, device=DEV)
     with pytest.raises(B.PftError) as e:
-        ctx.pft_adjoint(t, t, t.clone(), t.clone())
+        ctx.pft_adjoint(t, t, t.clone(), t.clone(), dL)  # the box derivative needs a periodic box
     assert e.value.status == B.PFT_E_UNSUPPORTED
     ctx.close()
     # the semi-implicit step: no linear response between absorbing walls, and
@@ -174,4 +175,32 @@ def test_semi_implicit_edwards_step_between_reflecting_walls(orc):
     ctx.pft_cl_step(g, None, B.pft_step(0.5, 1.2, 1.0, 4, 0, 1, 1, 1), phi)
     filt = orc.edwards_sis_update(p_or, Bv, om, host(phi), 0.5, 1.2, noise=True, seed=4, replica=0, step_=1)
     assert np.abs(host(g) - filt).max() <= 1e-12 * np.abs(filt).max()
+    ctx.close()
+
+
+ADJ_WALLS = [
+    # n, L, ns, f, bc, scheme
+    ((16, 12, 20), (2.0, 1.5, 2.5), 12, 0.41, (1, 0, 2), 0),
+    ((12, 16, 8), (1.5, 2.0, 1.0), 9, 0.5, (2, 1, 0), 1),
+    ((8, 12, 16), (1.0, 1.5, 2.0), 10, 0.03, (1, 1, 1), 0),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_WALLS, ids=[f"{c[0]}-{c[4]}-s{c[5]}" for c in ADJ_WALLS])
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_walled_adjoint_gradients(orc, case, prec):
+    n, L, ns, f, bc, scheme = case
+    say("walled adjoint", case, prec)
+    r = np.random.default_rng(60 + ns)
+    wp = 0.3 * r.standard_normal(n) + 0.1j * r.standard_normal(n)
+    wm = 0.5 * r.standard_normal(n) + 0.1j * r.standard_normal(n)
+    rp, rm, _ = orc.adjoint(oparams(orc, n, L, ns, f, bc, scheme), wp, wm)
+    ctx = B.Context(gparams(n, L, ns, f, prec, bc, scheme))
+    gp = torch.empty(n, dtype=torch.complex128, device=DEV)
+    gm = torch.empty_like(gp)
+    ctx.pft_adjoint(dev(wp), dev(wm), gp, gm, None, None, 3)
+    tol = 1e-10 if prec == B.PFT_C128 else 2e-5
+    assert np.abs(host(gp) - rp).max() <= tol * np.abs(rp).max()
+    assert np.abs(host(gm) - rm).max() <= tol * np.abs(rm).max()
+    assert ctx.pft_status_flags() == 0
     ctx.close()

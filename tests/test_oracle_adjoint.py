@@ -39,6 +39,26 @@ def test_field_gradient_fd(orc, scheme, f, ns):
                 assert abs(fd - g[site] * direction) <= 1e-7 * abs(g[site]) + 5e-10, (site, which, direction)
 
 
+@pytest.mark.parametrize("bc,scheme", [((1, 0, 2), 0), ((2, 1, 0), 1), ((1, 1, 1), 0)])
+def test_field_gradient_fd_with_walls(orc, bc, scheme):
+    """Between walls the steps diffuse through the walled operator (cosine /
+    sine modes), which is symmetric too: the same reverse mode, checked by
+    finite differences of the oracle's walled H."""
+    sh, L = (4, 6, 4), (2.0, 3.0, 2.5)
+    p = orc.Params(*sh, *L, 9, 0.41, 15.0, 2.0, scheme, False, bc)
+    wp, wm = fields(sh, 5)
+    gp, gm, dL = orc.adjoint(p, wp, wm)
+    assert dL is None
+    for site in [(0, 0, 0), (3, 5, 3), (2, 1, 2)]:
+        for which, g in ((0, gp), (1, gm)):
+            def H(e):
+                d = np.zeros(sh, complex)
+                d[site] = e
+                return orc.evaluate(p, wp + d, wm)["H"] if which == 0 else orc.evaluate(p, wp, wm + d)["H"]
+            fd = fd4(H, 3e-4)
+            assert abs(fd - g[site]) <= 1e-7 * abs(g[site]) + 5e-10, (site, which)
+
+
 @pytest.mark.parametrize("scheme,f,ns", CASES)
 def test_box_stress_fd(orc, scheme, f, ns):
     sh, L = (4, 6, 4), [2.0, 3.0, 2.5]
