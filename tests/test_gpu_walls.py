@@ -204,3 +204,30 @@ def test_walled_adjoint_gradients(orc, case, prec):
     assert np.abs(host(gm) - rm).max() <= tol * np.abs(rm).max()
     assert ctx.pft_status_flags() == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("storage", [B.PFT_STORE_Q, B.PFT_STORE_HOST])
+def test_walled_storage_modes_and_graph(storage):
+    """Walls with the other storage modes and with graph replay: the same
+    numbers as the default evaluation of the same walled context."""
+    n, L, ns, f, bc = (16, 12, 20), (2.0, 1.5, 2.5), 11, 0.35, (1, 0, 2)
+    r = np.random.default_rng(71)
+    wp = dev(0.3 * r.standard_normal(n) + 0.1j * r.standard_normal(n))
+    wm = dev(0.4 * r.standard_normal(n) + 0.1j * r.standard_normal(n))
+    base = B.Context(gparams(n, L, ns, f, B.PFT_C128, bc))
+    ref = {k: host(v) for k, v in base.evaluate(wp, wm).items()}
+    ga = torch.empty(n, dtype=torch.complex128, device=DEV)
+    gb = torch.empty_like(ga)
+    gQ = torch.empty(1, dtype=torch.complex128, device=DEV)
+    base.pft_evaluate_graph(wp, wm, ga, gb, gQ, 2)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(ga), ref["phiA"]) and np.array_equal(host(gQ), ref["Q"])
+    base.close()
+    p = B.Params(*n, *L, ns, f, 14.0, 2.0, B.PFT_C128, 0, B.PFT_DIBLOCK, 0.0, storage, bc)
+    ctx = B.Context(p)
+    got = {k: host(v) for k, v in ctx.evaluate(wp, wm).items()}
+    for k in ("phiA", "phiB"):
+        assert np.abs(got[k] - ref[k]).max() <= 1e-13, k
+    assert abs(got["Q"][0] - ref["Q"][0]) <= 1e-14 * abs(ref["Q"][0])
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
