@@ -137,7 +137,7 @@ typedef struct {
                         g = B/C + g_D(|k|^2) for the Edwards field; between
                         reflecting walls the modes of a walled axis are the
                         cosine modes, k = pi m / L (the filter runs on the
-                        even image of period 2L).  Batches accept 0 only. */
+                        even image of period 2L).  Batches accept both. */
 } pft_step;
 
 /* Create a context for one parameter set on the current HIP device.
@@ -327,14 +327,16 @@ const char* pft_batch_last_error(const pft_batch* batch);
 pft_status pft_batch_evaluate(pft_batch* batch, const double* const* w_plus, const double* const* w_minus,
                               double* const* phi_a, double* const* phi_b, double* Q, double* H);
 
-/* nsteps field steps of every replica (pft_cl_step semantics, in place on
- * the fields), replica r drawing noise with key (seed, replica + r) and step
- * numbers step, step+1, ....  The step is captured in a HIP graph on first
- * use and replayed; a call with other field pointers, log buffer or step
- * parameters re-captures.  QH_log (device, may be NULL): rows of n (Q, H)
- * complex128 pairs, row i for the i-th step of this call, up to log_rows
- * rows.  Asynchronous; pft_batch_sync waits.  Errors: PFT_E_INVALID,
- * PFT_E_DEVICE. */
+/* nsteps field steps of every replica (pft_cl_step semantics, explicit or
+ * semi-implicit by step->update, in place on the fields), replica r drawing
+ * noise with key (seed, replica + r) and step numbers step, step+1, ....  The
+ * step is captured in a HIP graph on first use and replayed; a call with
+ * other field pointers, log buffer or step parameters re-captures.  The
+ * semi-implicit step allocates each replica's filter buffers (one complex128
+ * field and the k tables) before its first capture.  QH_log (device, may be
+ * NULL): rows of n (Q, H) complex128 pairs, row i for the i-th step of this
+ * call, up to log_rows rows.  Asynchronous; pft_batch_sync waits.  Errors:
+ * PFT_E_INVALID (also update other than 0 or 1), PFT_E_NOMEM, PFT_E_DEVICE. */
 pft_status pft_batch_cl_steps(pft_batch* batch, double* const* w_plus, double* const* w_minus,
                               const pft_step* step, int32_t nsteps, double* QH_log, int64_t log_rows);
 pft_status pft_batch_sync(pft_batch* batch);

@@ -453,12 +453,14 @@ struct SisIncArgs {
     double two_over_chiN, ap, am, sp, sm, den_m;
     int noise;
     uint64_t seed, rep, step;
+    const uint64_t* step_dev;  // if set, *step_dev is added to step (graph-replayed batches)
     int edwards;
     double b_over_c;
 };
 
 __global__ void k_sis_increment(SisIncArgs a)
 {
+    if (a.step_dev) a.step += *a.step_dev;
     const int64_t ng = (a.M + 3) / 4;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += (int64_t)gridDim.x * blockDim.x) {
         double zp[4] = {0, 0, 0, 0}, zm[4] = {0, 0, 0, 0};
@@ -1943,6 +1945,10 @@ void free_all(pft_ctx* c)
 }  // namespace
 
 
+// The semi-implicit step (defined with the field steps below).
+static pft_status sis_prepare(pft_ctx* c);
+static pft_status sis_step(pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev = nullptr);
+
 // ================================================================ batches ==
 // Many independent replicas (uneven grids, contour step counts, f, chi N) run
 // together: replicas are grouped by grid shape; every pass of a group is one
@@ -1965,6 +1971,7 @@ struct BatchGroup {
     void* zd = nullptr;          // [dir 2][pos maxK+1][R] ZArgs (PArgs when fused)
     void* sd = nullptr;          // [dir 2][pos maxK][npass][R] SArgs
     void* jobs = nullptr;        // job tables for the small kernels
+    std::vector<UpdArgs> upd;    // field-step arguments per replica (host copy, for the semi-implicit step)
     size_t off_tab = 0, off_sum = 0, off_fin = 0, off_dens = 0, off_ham = 0, off_upd = 0;
 };
 
@@ -2155,13 +2162,14 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
     PFT_BHIP(b, hipMemcpy(base + g.off_dens, dens.data(), R * sizeof(dens[0]), hipMemcpyHostToDevice));
     PFT_BHIP(b, hipMemcpy(base + g.off_ham, ham.data(), R * sizeof(ham[0]), hipMemcpyHostToDevice));
     PFT_BHIP(b, hipMemcpy(base + g.off_upd, upd.data(), R * sizeof(upd[0]), hipMemcpyHostToDevice));
+    g.upd = std::move(upd);
     return PFT_OK;
 }
 
-// Enqueue one evaluation (and, if update, the field step) of one group on
-// its stream.
+// Enqueue one evaluation (and, if update, the field step: explicit, or
+// semi-implicit when sis) of one group on its stream.
 template <typename T>
-pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update)
+pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool sis)
 {
     const int R = (int)g.reps.size();
     hipStream_t s = g.s;
@@ -2202,21 +2210,33 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update)
                        reinterpret_cast<const HamJob*>(jb + g.off_ham));
     hipLaunchKernelGGL(k_ham_final_batch, dim3(1, R), dim3(kRedThreads), 0, s,
                        reinterpret_cast<const HamJob*>(jb + g.off_ham));
-    if (update)
+    if (update && !sis)
         hipLaunchKernelGGL(k_update_batch, dim3(grid_for((g.maxM + 3) / 4, 256), R), dim3(256), 0, s,
                            reinterpret_cast<const UpdArgs*>(jb + g.off_upd), b->counters);
     PFT_BHIP(b, hipGetLastError());
+    if (update && sis) {
+        // one linear-response filter per replica, on the group stream; the
+        // noise step is read from the batch's device counter
+        for (int ri = 0; ri < R; ++ri) {
+            pft_ctx* c = b->ctx[g.reps[ri]];
+            const hipStream_t own = c->stream;
+            c->stream = s;
+            const pft_status st = sis_step(c, g.upd[ri], b->counters);
+            c->stream = own;
+            if (st) return b->fail(st, "replica %d: %s", g.reps[ri], c->err.c_str());
+        }
+    }
     return PFT_OK;
 }
 
 // Fork the group streams off the batch stream, enqueue every group, join.
 template <typename T>
-pft_status batch_enqueue(pft_batch* b, bool update, const double2* logbuf, int64_t cap)
+pft_status batch_enqueue(pft_batch* b, bool update, bool sis, const double2* logbuf, int64_t cap)
 {
     PFT_BHIP(b, hipEventRecord(b->fork, b->own));
     for (BatchGroup& g : b->groups) {
         PFT_BHIP(b, hipStreamWaitEvent(g.s, b->fork, 0));
-        pft_status st = batch_enqueue_group<T>(b, g, update);
+        pft_status st = batch_enqueue_group<T>(b, g, update, sis);
         if (st) return st;
         PFT_BHIP(b, hipEventRecord(g.done, g.s));
         PFT_BHIP(b, hipStreamWaitEvent(b->own, g.done, 0));
@@ -2252,7 +2272,7 @@ pft_status batch_evaluate_t(pft_batch* b, const double* const* wp, const double*
     b->gwp.clear();  // the jobs no longer match a captured graph
     PFT_BHIP(b, hipEventRecord(b->in, b->stream));
     PFT_BHIP(b, hipStreamWaitEvent(b->own, b->in, 0));
-    pft_status s = batch_enqueue<T>(b, false, nullptr, 0);
+    pft_status s = batch_enqueue<T>(b, false, false, nullptr, 0);
     if (s) return s;
     PFT_BHIP(b, hipEventRecord(b->out, b->own));
     PFT_BHIP(b, hipStreamWaitEvent(b->stream, b->out, 0));
@@ -2267,7 +2287,8 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
                       std::equal(b->gwp.begin(), b->gwp.end(), wp) && std::equal(b->gwm.begin(), b->gwm.end(), wm) &&
                       b->glog == log && b->gcap == cap && b->gst.dt == st->dt &&
                       b->gst.lambda_plus == st->lambda_plus && b->gst.lambda_minus == st->lambda_minus &&
-                      b->gst.seed == st->seed && b->gst.replica == st->replica && b->gst.noise == st->noise;
+                      b->gst.seed == st->seed && b->gst.replica == st->replica && b->gst.noise == st->noise &&
+                      b->gst.update == st->update;
     if (!same) {
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -2280,8 +2301,13 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
         std::vector<LogJob> lj(b->n);
         for (int r = 0; r < b->n; ++r) lj[r] = {b->ctx[r]->scal, b->ctx[r]->scal + 1};
         PFT_BHIP(b, hipMemcpy(b->logj, lj.data(), lj.size() * sizeof(LogJob), hipMemcpyHostToDevice));
+        if (st->update == 1)  // the filter buffers must exist before the capture
+            for (int r = 0; r < b->n; ++r) {
+                const pft_status ps = sis_prepare(b->ctx[r]);
+                if (ps) return b->fail(ps, "replica %d: %s", r, b->ctx[r]->err.c_str());
+            }
         PFT_BHIP(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
-        pft_status s = batch_enqueue<T>(b, true, reinterpret_cast<const double2*>(log), cap);
+        pft_status s = batch_enqueue<T>(b, true, st->update == 1, reinterpret_cast<const double2*>(log), cap);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(b->own, &graph);
         if (s) {
@@ -2707,7 +2733,9 @@ pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, doubl
 // Semi-implicit step (Eqs. (10)-(11)) from the explicit step's arguments: the
 // local increment kernel, then the reciprocal-space filter of the w_+ (or
 // omega) increment in five axis passes over a work array.
-static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
+// Buffers of the semi-implicit step (allocated on first use; batches allocate
+// them before capturing their graphs).
+static pft_status sis_prepare(pft_ctx* c)
 {
     const pft_params& p = c->p;
     if (!c->sisbuf) {
@@ -2746,6 +2774,20 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
         }
         PFT_HIP(c, hipMemcpy(c->k2, k2.data(), k2.size() * sizeof(double), hipMemcpyHostToDevice));
     }
+    return PFT_OK;
+}
+
+// step_dev: device step counter added to the noise step (batches), or NULL.
+static pft_status sis_step(pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev)
+{
+    const pft_params& p = c->p;
+    pft_status ps0 = sis_prepare(c);
+    if (ps0) return ps0;
+    const bool walls = p.bc[0] || p.bc[1] || p.bc[2];
+    const int n[3] = {p.nx, p.ny, p.nz};
+    int ne[3];
+    for (int ax = 0; ax < 3; ++ax) ne[ax] = p.bc[ax] ? 2 * n[ax] : n[ax];
+    const int64_t Me = (int64_t)ne[0] * ne[1] * ne[2];
     SisIncArgs a{};
     a.wp = u.wp;
     a.wm = u.wm;
@@ -2763,6 +2805,7 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
     a.seed = u.seed;
     a.rep = u.rep;
     a.step = u.step;
+    a.step_dev = step_dev;
     a.edwards = u.edwards;
     a.b_over_c = u.b_over_c;
     {
@@ -3100,7 +3143,7 @@ pft_status pft_batch_cl_steps(pft_batch* b, double* const* w_plus, double* const
         return b->fail(PFT_E_INVALID, "pft_batch_cl_steps: bad arguments");
     if (!(step->dt >= 0) || !(step->lambda_plus >= 0) || !(step->lambda_minus >= 0))
         return b->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
-    if (step->update != 0) return b->fail(PFT_E_UNSUPPORTED, "batches take the explicit step only");
+    if (step->update != 0 && step->update != 1) return b->fail(PFT_E_INVALID, "update must be 0 or 1");
     const double* const* wp = const_cast<const double* const*>(w_plus);
     const double* const* wm = const_cast<const double* const*>(w_minus);
     return b->precision == PFT_C128 ? batch_steps_t<double>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0)

@@ -87,3 +87,46 @@ def test_batch_graph_steps_match_single_steps():
             assert abs(lg[k, r, 1] - Hs[k]) <= 1e-12 * (abs(Hs[k]) + w.C * np.prod(w.L))
         assert np.all(lg[2:] == 0)
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_batch_semi_implicit_steps_match_single_steps(prec):
+    """Semi-implicit steps (Eqs. (10)-(11)) in a batch graph, then an explicit
+    step (a new capture), against the single-context sequence with the same
+    noise stream."""
+    reps, params, fields = replica_set(5, 79, prec)
+    n = len(reps)
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+    log = torch.zeros((3, n, 2), dtype=torch.complex128, device=DEV)
+    bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.05, 1.0, 0.8, 31, 200, 4, 1, 1), 2, log)
+    bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.05, 1.0, 0.8, 31, 200, 6, 1, 0), 1, None)
+    bat.pft_batch_sync()
+    for r, w in enumerate(reps):
+        print("replica", r, w.n, w.ns, flush=True)
+        ctx = B.Context(params[r])
+        a, b = dev(fields[r][0]), dev(fields[r][1])
+        Qt = torch.empty(1, dtype=torch.complex128, device=DEV)
+        Ht = torch.empty_like(Qt)
+        Qs, Hs = [], []
+        for stepno, upd in ((4, 1), (5, 1), (6, 0)):
+            ctx.pft_cl_step(a, b, B.pft_step(0.05, 1.0, 0.8, 31, 200 + r, stepno, 1, upd), None, None, Qt, Ht)
+            Qs.append(complex(host(Qt)[0]))
+            Hs.append(complex(host(Ht)[0]))
+        assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        lg = host(log)
+        for k in range(2):
+            assert abs(lg[k, r, 0] - Qs[k]) <= 1e-12 * abs(Qs[k])
+            assert abs(lg[k, r, 1] - Hs[k]) <= 1e-12 * (abs(Hs[k]) + w.C * np.prod(w.L))
+        ctx.close()
+
+
+def test_batch_rejects_unknown_update():
+    reps, params, fields = replica_set(2, 80, B.PFT_C128)
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+    with pytest.raises(B.PftError):
+        bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.05, 1.0, 0.8, 31, 200, 4, 1, 2), 1, None)

@@ -115,13 +115,3 @@ def test_sis_scft_relaxation_large_steps(orc):
         wp, wm = orc.sis_update(p_or, wp, wm, ref["phiA"], ref["phiB"], dt)
         assert np.abs(host(gwp) - wp).max() <= 1e-10 and np.abs(host(gwm) - wm).max() <= 1e-10, it
     assert norms[-1] < 0.5 * norms[0]
-
-
-def test_sis_rejected_by_batches():
-    reps = inputs.batch_replicas(2, 3)
-    bat = B.Batch([B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, B.PFT_C64, B.PFT_RQM4) for w in reps])
-    wp = [dev(inputs.fields(w)[0]) for w in reps]
-    wm = [dev(inputs.fields(w)[1]) for w in reps]
-    with pytest.raises(B.PftError) as e:
-        bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1), 1)
-    assert e.value.status == B.PFT_E_UNSUPPORTED
