@@ -378,6 +378,14 @@ def batched_gain(binding, inputs, count: int, steps: int):
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
     out["batched_c64_graph"] = {"ms_per_field_step": ms, "value": site_steps / (ms * 1e-3)}
+    # the same batch with the semi-implicit field step (one filter per replica in the graph)
+    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 2 + steps, 1, 1), 1)  # capture
+    t0.record()
+    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 3 + steps, 1, 1), steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    out["batched_c64_graph_semi_implicit"] = {"ms_per_field_step": ms, "value": site_steps / (ms * 1e-3)}
     bat.close()
     del wp, wm
     # one at a time, complex128, plain launches

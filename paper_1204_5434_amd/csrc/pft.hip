@@ -458,7 +458,7 @@ struct SisIncArgs {
     double b_over_c;
 };
 
-__global__ void k_sis_increment(SisIncArgs a)
+__device__ __forceinline__ void sis_increment_body(SisIncArgs a)
 {
     if (a.step_dev) a.step += *a.step_dev;
     const int64_t ng = (a.M + 3) / 4;
@@ -485,6 +485,11 @@ __global__ void k_sis_increment(SisIncArgs a)
         }
     }
 }
+
+__global__ void k_sis_increment(SisIncArgs a) { sis_increment_body(a); }
+
+// Batched form: blockIdx.y is the replica.
+__global__ void k_sis_increment_batch(const SisIncArgs* __restrict__ jobs) { sis_increment_body(jobs[blockIdx.y]); }
 
 // Between reflecting walls the filter runs on the even mirror image of the
 // increment, of period 2L along each walled axis (ne = 2n there), where the
@@ -1947,7 +1952,9 @@ void free_all(pft_ctx* c)
 
 // The semi-implicit step (defined with the field steps below).
 static pft_status sis_prepare(pft_ctx* c);
-static pft_status sis_step(pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev = nullptr);
+static SisIncArgs sis_inc_args(const pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev);
+static pft::SisArgs sis_filter_args(const pft_ctx* c, const UpdArgs& u, double2* X, double2* W, int ne_z,
+                                    int64_t Me);
 
 // ================================================================ batches ==
 // Many independent replicas (uneven grids, contour step counts, f, chi N) run
@@ -1971,7 +1978,7 @@ struct BatchGroup {
     void* zd = nullptr;          // [dir 2][pos maxK+1][R] ZArgs (PArgs when fused)
     void* sd = nullptr;          // [dir 2][pos maxK][npass][R] SArgs
     void* jobs = nullptr;        // job tables for the small kernels
-    std::vector<UpdArgs> upd;    // field-step arguments per replica (host copy, for the semi-implicit step)
+    size_t off_sisinc = 0, off_sis = 0;  // semi-implicit step: [R] SisIncArgs, [5 passes][R] SisArgs
     size_t off_tab = 0, off_sum = 0, off_fin = 0, off_dens = 0, off_ham = 0, off_upd = 0;
 };
 
@@ -2154,6 +2161,8 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
     g.off_dens = place(R * sizeof(DensJob<T>));
     g.off_ham = place(R * sizeof(HamJob));
     g.off_upd = place(R * sizeof(UpdArgs));
+    g.off_sisinc = place(R * sizeof(SisIncArgs));
+    g.off_sis = place(5 * R * sizeof(pft::SisArgs));
     if (!g.jobs) PFT_BHIP(b, hipMalloc(&g.jobs, o));
     char* base = static_cast<char*>(g.jobs);
     PFT_BHIP(b, hipMemcpy(base + g.off_tab, tab.data(), R * sizeof(tab[0]), hipMemcpyHostToDevice));
@@ -2162,7 +2171,25 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
     PFT_BHIP(b, hipMemcpy(base + g.off_dens, dens.data(), R * sizeof(dens[0]), hipMemcpyHostToDevice));
     PFT_BHIP(b, hipMemcpy(base + g.off_ham, ham.data(), R * sizeof(ham[0]), hipMemcpyHostToDevice));
     PFT_BHIP(b, hipMemcpy(base + g.off_upd, upd.data(), R * sizeof(upd[0]), hipMemcpyHostToDevice));
-    g.upd = std::move(upd);
+    if (st && st->update == 1) {
+        // the filter buffers exist (sis_prepare ran for every replica); the
+        // noise step is read from the batch's device counter
+        std::vector<SisIncArgs> inc(R);
+        std::vector<pft::SisArgs> fil(5 * (size_t)R);
+        for (int ri = 0; ri < R; ++ri) {
+            const pft_ctx* c = b->ctx[g.reps[ri]];
+            inc[ri] = sis_inc_args(c, upd[ri], b->counters);
+            const pft::SisArgs f = sis_filter_args(c, upd[ri], c->sisbuf, upd[ri].wp, g.nz, c->M);
+            for (int kind = 0; kind < 5; ++kind) {
+                pft::SisArgs& e = fil[(size_t)kind * R + ri];
+                e = f;
+                if (!pft::sis_pass_layout(kind, g.nx, g.ny, g.nz, &e))
+                    return b->fail(PFT_E_UNSUPPORTED, "semi-implicit step: no kernel for this grid");
+            }
+        }
+        PFT_BHIP(b, hipMemcpy(base + g.off_sisinc, inc.data(), R * sizeof(inc[0]), hipMemcpyHostToDevice));
+        PFT_BHIP(b, hipMemcpy(base + g.off_sis, fil.data(), fil.size() * sizeof(fil[0]), hipMemcpyHostToDevice));
+    }
     return PFT_OK;
 }
 
@@ -2215,16 +2242,14 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool si
                            reinterpret_cast<const UpdArgs*>(jb + g.off_upd), b->counters);
     PFT_BHIP(b, hipGetLastError());
     if (update && sis) {
-        // one linear-response filter per replica, on the group stream; the
-        // noise step is read from the batch's device counter
-        for (int ri = 0; ri < R; ++ri) {
-            pft_ctx* c = b->ctx[g.reps[ri]];
-            const hipStream_t own = c->stream;
-            c->stream = s;
-            const pft_status st = sis_step(c, g.upd[ri], b->counters);
-            c->stream = own;
-            if (st) return b->fail(st, "replica %d: %s", g.reps[ri], c->err.c_str());
-        }
+        // the local increment, then the five filter passes, each one launch
+        // over the group's replicas
+        hipLaunchKernelGGL(k_sis_increment_batch, dim3(grid_for((g.maxM + 3) / 4, 256), R), dim3(256), 0, s,
+                           reinterpret_cast<const SisIncArgs*>(jb + g.off_sisinc));
+        PFT_BHIP(b, hipGetLastError());
+        const pft::SisArgs* fil = reinterpret_cast<const pft::SisArgs*>(jb + g.off_sis);
+        for (int kind = 0; kind < 5; ++kind)
+            PFT_BHIP(b, pft::launch_sis_pass_batch(kind, g.nx, g.ny, g.nz, fil + (size_t)kind * R, R, s));
     }
     return PFT_OK;
 }
@@ -2294,6 +2319,11 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
         b->graph = nullptr;
+        if (st->update == 1)  // the filter buffers must exist before the tables and the capture
+            for (int r = 0; r < b->n; ++r) {
+                const pft_status ps = sis_prepare(b->ctx[r]);
+                if (ps) return b->fail(ps, "replica %d: %s", r, b->ctx[r]->err.c_str());
+            }
         for (BatchGroup& g : b->groups) {
             pft_status s = batch_build_jobs<T>(b, g, wp, wm, nullptr, nullptr, nullptr, nullptr, st);
             if (s) return s;
@@ -2301,11 +2331,6 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
         std::vector<LogJob> lj(b->n);
         for (int r = 0; r < b->n; ++r) lj[r] = {b->ctx[r]->scal, b->ctx[r]->scal + 1};
         PFT_BHIP(b, hipMemcpy(b->logj, lj.data(), lj.size() * sizeof(LogJob), hipMemcpyHostToDevice));
-        if (st->update == 1)  // the filter buffers must exist before the capture
-            for (int r = 0; r < b->n; ++r) {
-                const pft_status ps = sis_prepare(b->ctx[r]);
-                if (ps) return b->fail(ps, "replica %d: %s", r, b->ctx[r]->err.c_str());
-            }
         PFT_BHIP(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
         pft_status s = batch_enqueue<T>(b, true, st->update == 1, reinterpret_cast<const double2*>(log), cap);
         hipGraph_t graph = nullptr;
@@ -2777,17 +2802,10 @@ static pft_status sis_prepare(pft_ctx* c)
     return PFT_OK;
 }
 
-// step_dev: device step counter added to the noise step (batches), or NULL.
-static pft_status sis_step(pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev)
+// Arguments of the local increment kernel of one context; step_dev: device
+// step counter added to the noise step (batches), or NULL.
+static SisIncArgs sis_inc_args(const pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev)
 {
-    const pft_params& p = c->p;
-    pft_status ps0 = sis_prepare(c);
-    if (ps0) return ps0;
-    const bool walls = p.bc[0] || p.bc[1] || p.bc[2];
-    const int n[3] = {p.nx, p.ny, p.nz};
-    int ne[3];
-    for (int ax = 0; ax < 3; ++ax) ne[ax] = p.bc[ax] ? 2 * n[ax] : n[ax];
-    const int64_t Me = (int64_t)ne[0] * ne[1] * ne[2];
     SisIncArgs a{};
     a.wp = u.wp;
     a.wm = u.wm;
@@ -2808,6 +2826,39 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u, const uint64_t* step_de
     a.step_dev = step_dev;
     a.edwards = u.edwards;
     a.b_over_c = u.b_over_c;
+    return a;
+}
+
+// Arguments of the reciprocal-space filter passes over X (Me sites, last
+// axis ne_z long), subtracting from W.
+static pft::SisArgs sis_filter_args(const pft_ctx* c, const UpdArgs& u, double2* X, double2* W, int ne_z,
+                                    int64_t Me)
+{
+    pft::SisArgs f{};
+    f.X = reinterpret_cast<cx<double>*>(X);
+    f.W = reinterpret_cast<cx<double>*>(W);
+    f.k2x = c->k2;
+    f.k2y = c->k2 + c->maxN;
+    f.k2z = c->k2 + 2 * (size_t)c->maxN;
+    f.nz = ne_z;
+    f.a = u.dtp;
+    f.g0 = u.edwards ? u.b_over_c : 0.0;
+    f.gD = 1.0;
+    f.inv_M = 1.0 / (double)Me;
+    return f;
+}
+
+static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
+{
+    const pft_params& p = c->p;
+    pft_status ps0 = sis_prepare(c);
+    if (ps0) return ps0;
+    const bool walls = p.bc[0] || p.bc[1] || p.bc[2];
+    const int n[3] = {p.nx, p.ny, p.nz};
+    int ne[3];
+    for (int ax = 0; ax < 3; ++ax) ne[ax] = p.bc[ax] ? 2 * n[ax] : n[ax];
+    const int64_t Me = (int64_t)ne[0] * ne[1] * ne[2];
+    const SisIncArgs a = sis_inc_args(c, u, nullptr);
     {
         ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
         hipLaunchKernelGGL(k_sis_increment, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
@@ -2826,17 +2877,7 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u, const uint64_t* step_de
         hipLaunchKernelGGL(k_sis_mirror, dim3(grid_for(Me, 256)), dim3(256), 0, c->stream, ma);
         PFT_HIP(c, hipGetLastError());
     }
-    pft::SisArgs f{};
-    f.X = reinterpret_cast<cx<double>*>(walls ? ma.X : c->sisbuf);
-    f.W = reinterpret_cast<cx<double>*>(walls ? ma.W : u.wp);
-    f.k2x = c->k2;
-    f.k2y = c->k2 + c->maxN;
-    f.k2z = c->k2 + 2 * (size_t)c->maxN;
-    f.nz = ne[2];
-    f.a = u.dtp;
-    f.g0 = u.edwards ? u.b_over_c : 0.0;
-    f.gD = 1.0;
-    f.inv_M = 1.0 / (double)Me;
+    const pft::SisArgs f = sis_filter_args(c, u, walls ? ma.X : c->sisbuf, walls ? ma.W : u.wp, ne[2], Me);
     for (int kind = 0; kind < 5; ++kind) {
         ProfScope ps(c, PFT_K_REDUCE, (kind == 4 ? 3.0 : 2.0) * sizeof(double2) * (double)Me);
         PFT_HIP(c, pft::launch_sis_pass(kind, ne[0], ne[1], ne[2], f, c->stream));

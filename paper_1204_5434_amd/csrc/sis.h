@@ -48,7 +48,7 @@ __device__ __forceinline__ double debye_gd(double x)
 
 // Contiguous lines (the z axis), laid out as in the z pass.
 template <int N1, int N2, int MODE>
-__global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_sis_z(SisArgs A)
+__device__ __forceinline__ void sis_z_body(const SisArgs& A)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<double>* sh = reinterpret_cast<cx<double>*>(smem_raw);
@@ -79,6 +79,20 @@ __global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_sis_z(SisArgs
     }
 }
 
+template <int N1, int N2, int MODE>
+__global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_sis_z(SisArgs A)
+{
+    sis_z_body<N1, N2, MODE>(A);
+}
+
+// Batched form: blockIdx.y selects the array (every array of one launch has
+// the same shape).
+template <int N1, int N2, int MODE>
+__global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_sis_z_batch(const SisArgs* __restrict__ tab)
+{
+    sis_z_body<N1, N2, MODE>(tab[blockIdx.y]);
+}
+
 // Filter factor of one x line: column (y, z) fixed, kx in natural order.
 struct SisFactor {
     const double* k2x;
@@ -91,7 +105,7 @@ struct SisFactor {
 
 // Strided columns (the x and y axes), laid out as in the strided passes.
 template <int N1, int N2, int MODE>
-__global__ __launch_bounds__((SShape<double, N2, 1>::kThreads)) void k_sis_s(SisArgs A)
+__device__ __forceinline__ void sis_s_body(const SisArgs& A)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<double>* sh = reinterpret_cast<cx<double>*>(smem_raw);
@@ -129,9 +143,29 @@ __global__ __launch_bounds__((SShape<double, N2, 1>::kThreads)) void k_sis_s(Sis
     }
 }
 
+template <int N1, int N2, int MODE>
+__global__ __launch_bounds__((SShape<double, N2, 1>::kThreads)) void k_sis_s(SisArgs A)
+{
+    sis_s_body<N1, N2, MODE>(A);
+}
+
+template <int N1, int N2, int MODE>
+__global__ __launch_bounds__((SShape<double, N2, 1>::kThreads)) void k_sis_s_batch(const SisArgs* __restrict__ tab)
+{
+    sis_s_body<N1, N2, MODE>(tab[blockIdx.y]);
+}
+
 // Launch one pass of the filter on an nx x ny x nz array (FP64): kind 0 =
 // z forward, 1 = y forward, 2 = x filter, 3 = y inverse, 4 = z inverse with
 // W -= result.
 hipError_t launch_sis_pass(int kind, int nx, int ny, int nz, SisArgs a, hipStream_t s);
+
+// Set the line layout fields of a (nlines, S, slab_stride, ncols, ntiles) for
+// pass kind on an nx x ny x nz array; false if the axis length has no kernel.
+bool sis_pass_layout(int kind, int nx, int ny, int nz, SisArgs* a);
+
+// The same pass over R arrays of one shape: tab (device) holds R argument
+// sets with their layout fields set by sis_pass_layout for this kind.
+hipError_t launch_sis_pass_batch(int kind, int nx, int ny, int nz, const SisArgs* tab, int R, hipStream_t s);
 
 }  // namespace pft
