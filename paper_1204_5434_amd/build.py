@@ -41,7 +41,7 @@ KERNEL_FILES = {
     "axis": ["fft.h", "kernels.h", "passes.inc", "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip",
              "passes_f32_alt.hip"],
     "yzpass": ["fft.h", "kernels.h", "planes.h", "planes.inc", "planes_f64.hip", "planes_f32.hip"],
-    "density": ["fft.h", "kernels.h", "pft.hip"],
+    "density": ["fft.h", "density.h"],
 }
 KIND_GROUP = {"zpass": "axis", "ypass": "axis", "xpass": "axis", "yzpass": "yzpass", "density": "density"}
 
