@@ -130,3 +130,29 @@ def test_batch_rejects_unknown_update():
     wm = [dev(f[1]) for f in fields]
     with pytest.raises(B.PftError):
         bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.05, 1.0, 0.8, 31, 200, 4, 1, 2), 1, None)
+
+
+def test_batch_semi_implicit_per_replica_boxes():
+    """Replicas that share a grid (one launch group) but not a box: each takes
+    the filter of its own k grid (and the Debye function at its own |k|^2)."""
+    W = inputs.Workload
+    reps = [W("a", (32, 24, 40), (3.0, 2.5, 5.0), 30, 0.4, 15.0, C=20.0, seed=5),
+            W("b", (32, 24, 40), (4.5, 3.0, 3.5), 44, 0.35, 18.0, C=20.0, seed=6),
+            W("c", (24, 24, 24), (3.0, 3.0, 3.0), 36, 0.45, 13.0, C=20.0, seed=7),
+            W("d", (32, 24, 40), (2.0, 6.0, 4.0), 25, 0.5, 20.0, C=20.0, seed=8)]
+    params = [B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, B.PFT_C128, B.PFT_RQM4) for w in reps]
+    fields = [inputs.fields(w) for w in reps]
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+    bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.2, 1.0, 0.5, 9, 40, 0, 1, 1), 3, None)
+    bat.pft_batch_sync()
+    for r, w in enumerate(reps):
+        print("replica", r, w.n, w.L, flush=True)
+        ctx = B.Context(params[r])
+        a, b = dev(fields[r][0]), dev(fields[r][1])
+        for stepno in range(3):
+            ctx.pft_cl_step(a, b, B.pft_step(0.2, 1.0, 0.5, 9, 40 + r, stepno, 1, 1))
+        assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        ctx.close()
