@@ -288,13 +288,14 @@ def evaluate(p: Params, wp, wm):
 
 def adjoint(p: Params, wp, wm):
     """(dH/dw_+, dH/dw_-, dH/dL[3]) by reverse mode through the split steps.
-    The field gradients hold with walls too (the steps diffuse through the
-    walled operator); dH/dL is that of a periodic box and is None with walls."""
+    With walls the steps diffuse through the walled operator (cosine / sine
+    modes, k = pi m / L along a walled axis), and dH/dL_a takes the axis
+    Laplacian in that axis's own mode basis."""
     wp, wm = _cfield(wp, p.shape), _cfield(wm, p.shape)
     gp, gm = np.empty_like(wp), np.empty_like(wp)
     dL = np.zeros(3, np.complex128)
     lib().or_adjoint(ctypes.byref(p._c()), _ptr(wp), _ptr(wm), _ptr(gp), _ptr(gm), _ptr(dL))
-    return gp, gm, (None if any(p.bc) else dL)
+    return gp, gm, dL
 
 
 # ------------------------------------------------------------- Edwards model --

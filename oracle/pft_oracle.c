@@ -285,10 +285,11 @@ void or_ksq_grid(const or_params *p, double *out)
  *   absorbing (Dirichlet): sin(pi m x / L), m = 1..N, the DST-II pair
  *     X_m = sum_n u_n sin(pi m (n+1/2)/N),
  *     u_n = (2/N) sum_{m<N} X_m sin(pi m (n+1/2)/N) + (1/N) X_N sin(pi N (n+1/2)/N);
- * each mode decays by exp(-(pi m / L)^2 h).  Written out as the definitions,
- * O(N^2) per line.
+ * each mode decays by exp(-(pi m / L)^2 h) (lap = 1: is multiplied by
+ * (pi m / L)^2 instead, which applies -d^2/dx^2).  Written out as the
+ * definitions, O(N^2) per line.
  */
-static void diffuse_walls_axis(const or_params *p, double h, cplx *u, int axis)
+static void walls_axis_modes(const or_params *p, double h, cplx *u, int axis, int lap)
 {
     const int n = (axis == 0) ? p->nx : (axis == 1) ? p->ny : p->nz;
     const double L = (axis == 0) ? p->lx : (axis == 1) ? p->ly : p->lz;
@@ -314,7 +315,7 @@ static void diffuse_walls_axis(const or_params *p, double h, cplx *u, int axis)
                     acc += in[i] * (dir ? sin(arg) : cos(arg));
                 }
                 const double k = pi * m / L;
-                X[m] = acc * exp(-k * k * h);
+                X[m] = acc * (lap ? k * k : exp(-k * k * h));
             }
             for (int i = 0; i < n; i++) {
                 cplx acc = 0.0;
@@ -331,6 +332,11 @@ static void diffuse_walls_axis(const or_params *p, double h, cplx *u, int axis)
         free(in);
         free(X);
     }
+}
+
+static void diffuse_walls_axis(const or_params *p, double h, cplx *u, int axis)
+{
+    walls_axis_modes(p, h, u, axis, 0);
 }
 
 /* The diffusion operator exp(h Laplacian) of Eq. (5), exact on the Fourier */
@@ -961,6 +967,43 @@ static cplx dbilinear(const or_params *p, double h, int axis, const cplx *u, con
     return acc / (double)M;
 }
 
+/* The same with walls on some axes.  On a walled axis the modes are
+ * k = pi m / L_a (sine or cosine), so again dk^2/dL_a = -2 k^2 / L_a and
+ *   dD_h/dL_a = (2 h / L_a) (-d^2/dx_a^2) D_h,
+ * the axis Laplacian taken in that axis's own mode basis (1-D DFT on a
+ * periodic axis, cosine / sine modes on a walled one):
+ *   u^T (dD_h/dL_a) v = (2 h / L_a) sum_x u(x) [(-d^2/dx_a^2) D_h v](x). */
+static cplx dbilinear_walls(const or_params *p, double h, int axis, const cplx *u, const cplx *v)
+{
+    const int64_t M = grid_m(p);
+    const int n = (axis == 0) ? p->nx : (axis == 1) ? p->ny : p->nz;
+    const double L = (axis == 0) ? p->lx : (axis == 1) ? p->ly : p->lz;
+    cplx *t = (cplx *)malloc(sizeof(cplx) * M);
+    memcpy(t, v, sizeof(cplx) * M);
+    or_diffuse(p, h, t);
+    if (p->bc[axis]) {
+        walls_axis_modes(p, 0.0, t, axis, 1);
+    } else {
+        fft_axis(t, p->nx, p->ny, p->nz, axis, -1);
+        for (int64_t x = 0; x < M; x++) {
+            const int64_t j = (axis == 0) ? x / ((int64_t)p->ny * p->nz) : (axis == 1) ? (x / p->nz) % p->ny : x % p->nz;
+            const double k = OR_TWO_PI * or_mode((int32_t)j, n) / L;
+            t[x] *= k * k / (double)n;
+        }
+        fft_axis(t, p->nx, p->ny, p->nz, axis, +1);
+    }
+    cplx acc = 0.0;
+    for (int64_t x = 0; x < M; x++) acc += u[x] * t[x];
+    free(t);
+    return 2.0 * h / L * acc;
+}
+
+static cplx dbil(const or_params *p, double h, int axis, const cplx *u, const cplx *v)
+{
+    if (p->bc[0] || p->bc[1] || p->bc[2]) return dbilinear_walls(p, h, axis, u, v);
+    return dbilinear(p, h, axis, u, v);
+}
+
 static void copy_mul(cplx *dst, const cplx *src, const cplx *w, double a, int64_t M)
 {
     for (int64_t x = 0; x < M; x++) dst[x] = src[x] * cexp(-w[x] * a);
@@ -1006,7 +1049,7 @@ int or_adjoint(const or_params *p, const cplx *wp, const cplx *wm, cplx *dHdwp, 
         if (p->scheme == OR_SPLIT2) {
             for (int64_t x = 0; x < M; x++)
                 g[x] += -(hj / 2) * lam[x] * Fq[x] - (hj / 2) * Fl[x] * q[x];
-            for (int a = 0; a < 3; a++) dQdL[a] += dbilinear(p, hj, a, e2l, e2q);
+            for (int a = 0; a < 3; a++) dQdL[a] += dbil(p, hj, a, e2l, e2q);
             continue;
         }
         /* half path: A = D_{h/2} E_{h/4} (.), H = E_{h/4} D_{h/2} E_{h/2} A */
@@ -1027,8 +1070,8 @@ int or_adjoint(const or_params *p, const cplx *wp, const cplx *wm, cplx *dHdwp, 
             g[x] += (4.0 / 3.0) * half - (1.0 / 3.0) * full;
         }
         for (int a = 0; a < 3; a++)
-            dQdL[a] += (4.0 / 3.0) * (dbilinear(p, hj / 2, a, e4l, e2Aq) + dbilinear(p, hj / 2, a, e2Al, e4q))
-                       - (1.0 / 3.0) * dbilinear(p, hj, a, e2l, e2q);
+            dQdL[a] += (4.0 / 3.0) * (dbil(p, hj / 2, a, e4l, e2Aq) + dbil(p, hj / 2, a, e2Al, e4q))
+                       - (1.0 / 3.0) * dbil(p, hj, a, e2l, e2q);
     }
     const double V = p->lx * p->ly * p->lz, dV = V / (double)M;
     cplx S = 0.0;
