@@ -86,8 +86,8 @@ typedef struct {
  * list (else PFT_E_UNSUPPORTED).  Walled contexts run the axis
  * schedule on walled y or z axes; the semi-implicit step takes reflecting
  * walls (modes of the cosine basis) when 2N is in the axis list, not
- * absorbing ones; pft_adjoint gives dH/dw with walls but dH/dL for periodic
- * boxes only; pft_debug_kgrid and batches accept periodic boxes only
+ * absorbing ones; pft_adjoint gives dH/dw and dH/dL with walls (walled
+ * modes k = pi m / L); pft_debug_kgrid and batches accept periodic boxes only
  * (PFT_E_UNSUPPORTED). */
 typedef enum { PFT_PERIODIC = 0, PFT_REFLECTING = 1, PFT_ABSORBING = 2 } pft_boundary;
 
@@ -253,9 +253,11 @@ pft_status pft_cl_step(pft_ctx* ctx, double* w_plus, double* w_minus, const pft_
  * dH_dL -- 3 complex128 (may be NULL): dH/dL_x, dH/dL_y, dH/dL_z with each box
  * edge varied alone and the field values on the grid held fixed (the diagonal
  * box stress times the volume over the edge); H -- complex128 (may be NULL),
- * the Hamiltonian of these fields.  With walls the field derivatives hold (the
- * walled diffusion is symmetric too) and dH_dL must be NULL.  Overwrites the
- * context's field tables and
+ * the Hamiltonian of these fields.  With walls both hold: the walled
+ * diffusion is symmetric too, and a walled axis's modes k = pi m / L scale
+ * with 1/L as the periodic ones do, so its stress pass applies -d^2/dx^2 in
+ * the cosine / sine basis (the edge varied between fixed walls, the
+ * cell-centred grid scaling with it).  Overwrites the context's field tables and
  * Q, so pft_densities / pft_hamiltonian need a new pft_propagate afterwards.
  * Errors: PFT_E_INVALID, PFT_E_NOMEM, PFT_E_DEVICE. */
 pft_status pft_adjoint(pft_ctx* ctx, const double* w_plus, const double* w_minus, int32_t ckpt_every,

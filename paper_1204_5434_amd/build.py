@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libpft.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["pft.hip", "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip", "passes_f32_alt.hip",
            "planes_f64.hip", "planes_f32.hip", "sis.hip", "passes_walls_f64.hip", "passes_walls_f32.hip",
-           "stress_f64.hip", "stress_f32.hip"]
+           "stress_f64.hip", "stress_f32.hip", "stress_walls_f64.hip", "stress_walls_f32.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

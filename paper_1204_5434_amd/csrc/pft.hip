@@ -1433,13 +1433,14 @@ std::vector<T> axis_factors(int n, double L, double h)
 // beta_m = (g_m - g_{n-m}) exp(i pi m / n) / 2, with g_m = exp(-(pi m / L)^2 h)
 // for the cosine modes of reflecting walls and g_m = exp(-(pi (n - m) / L)^2 h)
 // for the sine modes of absorbing walls (alpha_0 = g_0, beta_0 = 0), all / n.
+// lap: g_m = k^2 of the same modes instead (-d^2/dx^2, for the box derivative).
 template <typename T>
-std::vector<T> wall_factors(int n, double L, double h, int bc)
+std::vector<T> wall_factors(int n, double L, double h, int bc, bool lap = false)
 {
     auto g = [&](int m) {
         const double mode = bc == PFT_ABSORBING ? (double)(n - m) : (double)m;
         const double k = kPi * mode / L;
-        return std::exp(-k * k * h) / n;
+        return (lap ? k * k : std::exp(-k * k * h)) / n;
     };
     std::vector<T> ab(3 * (size_t)n);
     for (int m = 0; m < n; ++m) {
@@ -1474,13 +1475,20 @@ pft_status upload_factors(pft_ctx* c, int hid, double h)
     return PFT_OK;
 }
 
-// Spectral -d^2/dx_a^2 per axis, (2 pi m / L_a)^2 / N_a, in table slot 4.
+// Spectral -d^2/dx_a^2 per axis, (2 pi m / L_a)^2 / N_a, in table slot 4
+// (walled axes: the pair factors of (pi m / L_a)^2 / N_a).
 template <typename T>
 pft_status upload_second_derivative(pft_ctx* c)
 {
     const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
     const double L[3] = {c->p.lx, c->p.ly, c->p.lz};
     for (int ax = 0; ax < 3; ++ax) {
+        if (c->p.bc[ax]) {
+            const std::vector<T> g = wall_factors<T>(n[ax], L[ax], 0.0, c->p.bc[ax], true);
+            PFT_HIP(c, hipMemcpy(const_cast<T*>(gptr<T>(c, 4, 0, ax)), g.data(), g.size() * sizeof(T),
+                                 hipMemcpyHostToDevice));
+            continue;
+        }
         std::vector<T> g(n[ax]);
         for (int j = 0; j < n[ax]; ++j) {
             const int m = (j <= n[ax] / 2) ? j : j - n[ax];
@@ -1716,7 +1724,10 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
                 sp.coef[2] = rqm4 ? -2.0 / 3.0 * r : 2.0 * r;
                 sp.d2 = dtab(ax);
                 sp.part = c->adjAcc + (size_t)ax * np;
-                PFT_HIP(c, pft::launch_stress<T>(ax, c->p.nx, c->p.ny, c->p.nz, sp, c->stream));
+                if (c->p.bc[ax])
+                    PFT_HIP(c, pft::launch_stress_walls<T>(ax, c->p.bc[ax], c->p.nx, c->p.ny, c->p.nz, sp, c->stream));
+                else
+                    PFT_HIP(c, pft::launch_stress<T>(ax, c->p.nx, c->p.ny, c->p.nz, sp, c->stream));
             }
         }
         cur = 1 - cur;
@@ -2953,8 +2964,6 @@ pft_status pft_adjoint(pft_ctx* c, const double* wp, const double* wm, int32_t c
     if (ckpt_every < 0) return c->fail(PFT_E_INVALID, "pft_adjoint: ckpt_every must be >= 0");
     if (c->p.model != PFT_DIBLOCK) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: diblock model only");
     if (c->p.storage != PFT_STORE_BOTH) return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: needs both stores");
-    if (dL && (c->p.bc[0] || c->p.bc[1] || c->p.bc[2]))
-        return c->fail(PFT_E_UNSUPPORTED, "pft_adjoint: the box derivative needs a periodic box (pass dH_dL = NULL)");
     int Kc = ckpt_every;
     if (Kc == 0) Kc = (int)std::ceil(std::sqrt((double)c->K));
     Kc = std::max(1, std::min(Kc, c->K));

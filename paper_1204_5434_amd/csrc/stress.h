@@ -14,6 +14,13 @@
 // capture has its own row of workgroups (blockIdx.y); every workgroup adds its
 // FP64 sum to a partial slot of its own, summed over the steps and reduced
 // once at the end.
+// Along a walled axis (EXT = 1 reflecting, 2 absorbing) the modes are
+// k = pi m / L_a, which scale with 1/L_a as well, so the same sum holds with
+// -d^2/dx_a^2 taken in the cosine / sine basis: the line is loaded in the
+// reordered, sign-flipped order of the walled passes and transformed with
+// the paired factors of (pi m / L_a)^2 / N_a; the dot with the partner runs
+// over the same reordered points (the reordering is a permutation and the
+// signs square to one), so nothing is reordered back.
 #pragma once
 
 #include "kernels.h"
@@ -28,7 +35,8 @@ struct StressPass {
     const cx<T>* lam;   // lambda_{j+1}
     const cx<T>* Alam;  // the adjoint-side capture A (Richardson step only)
     const cx<T>* E4;    // the step's E4 table
-    const T* d2;        // (2 pi m / L_a)^2 / N_a in natural order
+    const T* d2;        // (2 pi m / L_a)^2 / N_a in natural order; walled: the pair
+                        // factors (alpha, beta re, beta im) per m of (pi m / L_a)^2 / N_a
     int64_t nlines;     // z pass: lines of nz contiguous points
     int64_t S;          // strided passes: element stride along the lines
     int64_t slab_stride;
@@ -89,7 +97,7 @@ __device__ __forceinline__ double2 stress_partner(const StressPass<T>& A, int i,
 }
 
 // Lines along z (contiguous), laid out as in the z pass.
-template <typename T, int N1, int N2>
+template <typename T, int N1, int N2, int EXT>
 __global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_stress_z(StressPass<T> A)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -100,18 +108,20 @@ __global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_stress_z(Stre
     const int t = threadIdx.x % N2, l = threadIdx.x / N2;
     const int64_t line = (int64_t)blockIdx.x * LPW + l;
     const bool act = line < A.nlines;
-    const int64_t base = line * N + t;
+    auto pos = [&](int r) { return line * N + ext_index<EXT, N>(r * N2 + t); };
     const LayZ<N1, N2> lay{l};
     const int i = A.first + (int)blockIdx.y;  // one capture per workgroup row
     CSum re, im;
     cx<T> a[N1];
     sfor<0, N1>([&](auto I) {
-        a[decltype(I)::value] = act ? A.X[i][base + decltype(I)::value * N2] : cx<T>{T(0), T(0)};
+        constexpr int r = decltype(I)::value;
+        a[r] = act ? ext_sign<EXT, N, T>(r * N2 + t) * A.X[i][pos(r)] : cx<T>{T(0), T(0)};
     });
-    diffuse<N1, N2>(a, t, sh, lay, A.d2);
+    line_diffuse<EXT, N1, N2>(a, t, sh, lay, A.d2);
     if (act) {
         sfor<0, N1>([&](auto I) {
-            const double2 v = mul2(stress_partner(A, i, base + decltype(I)::value * N2), wide2(a[decltype(I)::value]));
+            constexpr int r = decltype(I)::value;
+            const double2 v = mul2(stress_partner(A, i, pos(r)), wide2(ext_sign<EXT, N, T>(r * N2 + t) * a[r]));
             re.add(A.coef[i] * v.x);
             im.add(A.coef[i] * v.y);
         });
@@ -125,9 +135,10 @@ __global__ __launch_bounds__((ZShape<N1, N2, 1>::kThreads)) void k_stress_z(Stre
 }
 
 // Strided lines along x or y, laid out as in the strided passes.
-template <typename T, int N1, int N2>
+template <typename T, int N1, int N2, int EXT>
 __global__ __launch_bounds__((SShape<T, N2, 1>::kThreads)) void k_stress_s(StressPass<T> A)
 {
+    constexpr int N = N1 * N2;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     constexpr int TC = SShape<T, N2, 1>::kCols;
     constexpr int NT = SShape<T, N2, 1>::kThreads;
@@ -137,19 +148,21 @@ __global__ __launch_bounds__((SShape<T, N2, 1>::kThreads)) void k_stress_s(Stres
     const int slab = blockIdx.x / A.ntiles, tile = blockIdx.x % A.ntiles;
     const int col = tile * TC + c;
     const bool act = col < A.ncols;
-    const int64_t base = (int64_t)slab * A.slab_stride + col + (int64_t)t * A.S;
-    const int64_t step = (int64_t)N2 * A.S;
+    const int64_t base = (int64_t)slab * A.slab_stride + col;
+    auto pos = [&](int r) { return base + (int64_t)ext_index<EXT, N>(r * N2 + t) * A.S; };
     const LayS<N2, TC> lay{c};
     const int i = A.first + (int)blockIdx.y;  // one capture per workgroup row
     CSum re, im;
     cx<T> a[N1];
     sfor<0, N1>([&](auto I) {
-        a[decltype(I)::value] = act ? A.X[i][base + decltype(I)::value * step] : cx<T>{T(0), T(0)};
+        constexpr int r = decltype(I)::value;
+        a[r] = act ? ext_sign<EXT, N, T>(r * N2 + t) * A.X[i][pos(r)] : cx<T>{T(0), T(0)};
     });
-    diffuse<N1, N2>(a, t, sh, lay, A.d2);
+    line_diffuse<EXT, N1, N2>(a, t, sh, lay, A.d2);
     if (act) {
         sfor<0, N1>([&](auto I) {
-            const double2 v = mul2(stress_partner(A, i, base + decltype(I)::value * step), wide2(a[decltype(I)::value]));
+            constexpr int r = decltype(I)::value;
+            const double2 v = mul2(stress_partner(A, i, pos(r)), wide2(ext_sign<EXT, N, T>(r * N2 + t) * a[r]));
             re.add(A.coef[i] * v.x);
             im.add(A.coef[i] * v.y);
         });
@@ -167,6 +180,10 @@ __global__ __launch_bounds__((SShape<T, N2, 1>::kThreads)) void k_stress_s(Stres
 // stress_blocks() partial slots (workgroups per capture times three).
 template <typename T>
 hipError_t launch_stress(int axis, int nx, int ny, int nz, StressPass<T> a, hipStream_t s);
+// The same along a walled axis (ext = 1 reflecting, 2 absorbing; d2 holds the
+// pair factors).
+template <typename T>
+hipError_t launch_stress_walls(int axis, int ext, int nx, int ny, int nz, StressPass<T> a, hipStream_t s);
 template <typename T>
 int64_t stress_blocks(int axis, int nx, int ny, int nz);
 

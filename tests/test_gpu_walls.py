@@ -99,14 +99,6 @@ def test_walled_evaluation(orc, case, prec):
 
 
 def test_walled_rejections():
-    p = gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (1, 0, 0))
-    ctx = B.Context(p)
-    t = torch.zeros((16, 16, 16), dtype=torch.complex128, device=DEV)
-    dL = torch.empty(3, dtype=torch.complex128, device=DEV)
-    with pytest.raises(B.PftError) as e:
-        ctx.pft_adjoint(t, t, t.clone(), t.clone(), dL)  # the box derivative needs a periodic box
-    assert e.value.status == B.PFT_E_UNSUPPORTED
-    ctx.close()
     # the semi-implicit step: no linear response between absorbing walls, and
     # reflecting walls need a kernel for the image length 2n
     for bc, n in (((0, 2, 0), (16, 16, 16)), ((1, 0, 0), (80, 8, 8))):
@@ -116,8 +108,8 @@ def test_walled_rejections():
             ctx.pft_cl_step(t.clone(), t.clone(), B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1))
         assert e.value.status == B.PFT_E_UNSUPPORTED
         ctx.close()
-    with pytest.raises(B.PftError) as e:
-        B.Batch([p])
+    with pytest.raises(B.PftError) as e:  # batches take periodic boxes
+        B.Batch([gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (1, 0, 0))])
     assert e.value.status == B.PFT_E_UNSUPPORTED
     for bad, status in (((36, 16, 16), B.PFT_E_UNSUPPORTED), ((176, 16, 16), B.PFT_E_UNSUPPORTED)):
         with pytest.raises(B.PftError) as e:
@@ -183,6 +175,7 @@ ADJ_WALLS = [
     ((16, 12, 20), (2.0, 1.5, 2.5), 12, 0.41, (1, 0, 2), 0),
     ((12, 16, 8), (1.5, 2.0, 1.0), 9, 0.5, (2, 1, 0), 1),
     ((8, 12, 16), (1.0, 1.5, 2.0), 10, 0.03, (1, 1, 1), 0),
+    ((20, 8, 12), (2.5, 1.0, 1.5), 11, 0.37, (2, 2, 2), 0),
 ]
 
 
@@ -194,14 +187,20 @@ def test_walled_adjoint_gradients(orc, case, prec):
     r = np.random.default_rng(60 + ns)
     wp = 0.3 * r.standard_normal(n) + 0.1j * r.standard_normal(n)
     wm = 0.5 * r.standard_normal(n) + 0.1j * r.standard_normal(n)
-    rp, rm, _ = orc.adjoint(oparams(orc, n, L, ns, f, bc, scheme), wp, wm)
+    rp, rm, rL = orc.adjoint(oparams(orc, n, L, ns, f, bc, scheme), wp, wm)
     ctx = B.Context(gparams(n, L, ns, f, prec, bc, scheme))
     gp = torch.empty(n, dtype=torch.complex128, device=DEV)
     gm = torch.empty_like(gp)
-    ctx.pft_adjoint(dev(wp), dev(wm), gp, gm, None, None, 3)
+    dL = torch.empty(3, dtype=torch.complex128, device=DEV)
+    ctx.pft_adjoint(dev(wp), dev(wm), gp, gm, dL, None, 3)
     tol = 1e-10 if prec == B.PFT_C128 else 2e-5
     assert np.abs(host(gp) - rp).max() <= tol * np.abs(rp).max()
     assert np.abs(host(gm) - rm).max() <= tol * np.abs(rm).max()
+    # the box derivative between walls (walled axes in their cosine / sine
+    # modes), on the scale of its extensive terms as for a periodic box
+    C, V, dLh = 2.0, np.prod(L), host(dL)
+    for a in range(3):
+        assert abs(dLh[a] - rL[a]) <= tol * (abs(rL[a]) + C * V / L[a]), (a, dLh[a], rL[a])
     assert ctx.pft_status_flags() == 0
     ctx.close()
 
