@@ -313,13 +313,16 @@ def walls_run(binding, w, wp, wm, steps: int, warmup: int):
 def adjoint_run(binding, inputs, steps: int):
     """The gradient workload (96^3, Ns = 128, f = 0.3, checkpoints every 11
     steps): one reverse-mode pass (dH/dw+-, dH/dL and H) against one plain
-    evaluation (propagate + densities) of the same state, both precisions."""
+    evaluation (propagate + densities) of the same state, both precisions,
+    and in complex double between reflecting walls normal to z."""
     import torch
     w = inputs.GRAD96
     wp, wm = (torch.from_numpy(a).to("cuda") for a in inputs.fields(w))
     out = {"workload": w.name, "grid": list(w.n), "ns": w.ns, "f": w.f, "ckpt_every": 11}
-    for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
-        ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4))
+    for name, prec, bc in (("f64", binding.PFT_C128, (0, 0, 0)), ("f32", binding.PFT_C64, (0, 0, 0)),
+                           ("f64_film_z_reflecting", binding.PFT_C128, (0, 0, 1))):
+        ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4,
+                                             binding.PFT_DIBLOCK, 0.0, binding.PFT_STORE_BOTH, bc))
         gp = torch.empty(w.n, dtype=torch.complex128, device="cuda")
         gm = torch.empty_like(gp)
         dL = torch.empty(3, dtype=torch.complex128, device="cuda")
