@@ -87,8 +87,9 @@ typedef struct {
  * schedule on walled y or z axes; the semi-implicit step takes reflecting
  * walls (modes of the cosine basis) when 2N is in the axis list, not
  * absorbing ones; pft_adjoint gives dH/dw and dH/dL with walls (walled
- * modes k = pi m / L); pft_debug_kgrid and batches accept periodic boxes only
- * (PFT_E_UNSUPPORTED). */
+ * modes k = pi m / L); batches take walls with the explicit step;
+ * pft_debug_kgrid and the batched semi-implicit step accept periodic boxes
+ * only (PFT_E_UNSUPPORTED). */
 typedef enum { PFT_PERIODIC = 0, PFT_REFLECTING = 1, PFT_ABSORBING = 2 } pft_boundary;
 
 /* Where the propagators live (diblock model).
@@ -306,7 +307,7 @@ pft_status pft_noise_normals(uint64_t seed, uint64_t replica, uint64_t step, int
 /* ---- batches of independent replicas --------------------------------------
  * Many independent systems (SCFT candidates or complex-Langevin replicas,
  * each its own pft_params: grid, box, ns, f, chiN, C) advanced together.
- * Replicas with the same grid shape form a group; every axis pass of a group
+ * Replicas with the same grid shape and walls form a group; every axis pass of a group
  * is one launch over all its replicas (per-replica arguments come from device
  * tables, uneven contour step counts are masked); groups run on their own
  * streams; one field step of the whole batch is captured in a HIP graph and
@@ -315,7 +316,8 @@ pft_status pft_noise_normals(uint64_t seed, uint64_t replica, uint64_t step, int
  * (Sec. VI notes the GPU only pays off above 512-2048 plane waves). */
 typedef struct pft_batch pft_batch;
 
-/* params: n parameter sets (host memory).  Errors: PFT_E_INVALID (n < 1,
+/* params: n parameter sets (host memory): the diblock model with both stores,
+ * periodic or walled.  Errors: PFT_E_INVALID (n < 1,
  * mixed precision/scheme, or a bad parameter set), PFT_E_UNSUPPORTED,
  * PFT_E_NOMEM, PFT_E_DEVICE; on failure *out = NULL and nothing is kept. */
 pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_stream, pft_batch** out);
@@ -338,7 +340,8 @@ pft_status pft_batch_evaluate(pft_batch* batch, const double* const* w_plus, con
  * field and the k tables) before its first capture.  QH_log (device, may be
  * NULL): rows of n (Q, H) complex128 pairs, row i for the i-th step of this
  * call, up to log_rows rows.  Asynchronous; pft_batch_sync waits.  Errors:
- * PFT_E_INVALID (also update other than 0 or 1), PFT_E_NOMEM, PFT_E_DEVICE. */
+ * PFT_E_INVALID (also update other than 0 or 1), PFT_E_UNSUPPORTED (the
+ * semi-implicit step with a walled replica), PFT_E_NOMEM, PFT_E_DEVICE. */
 pft_status pft_batch_cl_steps(pft_batch* batch, double* const* w_plus, double* const* w_minus,
                               const pft_step* step, int32_t nsteps, double* QH_log, int64_t log_rows);
 pft_status pft_batch_sync(pft_batch* batch);

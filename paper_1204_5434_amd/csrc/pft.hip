@@ -20,6 +20,7 @@
 #include "planes.h"
 #include "sis.h"
 #include "stress.h"
+#include "walls_batch.h"
 
 using pft::cdiv;
 using pft::cmul;
@@ -1916,6 +1917,7 @@ namespace {
 
 struct BatchGroup {
     int nx = 0, ny = 0, nz = 0;
+    int bc[3] = {0, 0, 0};       // walls of the group's replicas (fused groups have none on y and z)
     std::vector<int> reps;
     int maxK = 0;
     int64_t maxM = 0;
@@ -2032,6 +2034,9 @@ pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
                         continue;
                     }
                     d = g.fused ? sa[1] : sa[k];  // fused: the x pass alone
+                    const int axk = g.sp_axis[k];
+                    if (g.bc[axk])  // walled kernels take the default tile
+                        d.ntiles = pft::spass_tiles<T>(axk == 0 ? g.nx : g.ny, 0, d.ncols);
                 }
             }
         }
@@ -2165,6 +2170,7 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool si
     auto zlaunch = [&](int dir, int p) -> hipError_t {
         const size_t at = ((size_t)dir * (g.maxK + 1) + p) * R;
         if (g.fused) return pft::launch_yzpass_batch<T>(g.ny, g.nx, pd + at, R, s);
+        if (g.bc[2]) return pft::launch_zpass_walls_batch<T>(g.nz, g.bc[2], nlines, zd + at, R, s);
         return pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + at, R, s);
     };
     for (int dir = 0; dir < 2; ++dir) {
@@ -2172,8 +2178,11 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool si
         for (int p = 0; p < g.maxK; ++p) {
             for (int k = 0; k < g.npass; ++k) {
                 const int ax = g.sp_axis[k];
-                PFT_BHIP(b, pft::launch_spass_batch<T>(ax, n_ax[ax], g.var[ax], ncols[ax], nslabs[ax],
-                                                       sd + (((size_t)dir * g.maxK + p) * g.npass + k) * R, R, s));
+                const pft::SArgs<T>* at = sd + (((size_t)dir * g.maxK + p) * g.npass + k) * R;
+                if (g.bc[ax])
+                    PFT_BHIP(b, pft::launch_spass_walls_batch<T>(ax, n_ax[ax], g.bc[ax], ncols[ax], nslabs[ax], at, R, s));
+                else
+                    PFT_BHIP(b, pft::launch_spass_batch<T>(ax, n_ax[ax], g.var[ax], ncols[ax], nslabs[ax], at, R, s));
             }
             PFT_BHIP(b, zlaunch(dir, p + 1));
         }
@@ -3022,9 +3031,7 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     for (int r = 1; r < n; ++r)
         if (params[r].precision != params[0].precision || params[r].scheme != params[0].scheme) return PFT_E_INVALID;
     for (int r = 0; r < n; ++r)
-        if (params[r].model != PFT_DIBLOCK || params[r].storage != PFT_STORE_BOTH || params[r].bc[0] ||
-            params[r].bc[1] || params[r].bc[2])
-            return PFT_E_UNSUPPORTED;
+        if (params[r].model != PFT_DIBLOCK || params[r].storage != PFT_STORE_BOTH) return PFT_E_UNSUPPORTED;
     pft_batch* b = new (std::nothrow) pft_batch();
     if (!b) return PFT_E_NOMEM;
     b->n = n;
@@ -3042,13 +3049,16 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
         const pft_params& p = params[r];
         BatchGroup* g = nullptr;
         for (BatchGroup& x : b->groups)
-            if (x.nx == p.nx && x.ny == p.ny && x.nz == p.nz) g = &x;
+            if (x.nx == p.nx && x.ny == p.ny && x.nz == p.nz && x.bc[0] == p.bc[0] && x.bc[1] == p.bc[1] &&
+                x.bc[2] == p.bc[2] && x.fused == b->ctx[r]->fused)
+                g = &x;
         if (!g) {
             b->groups.emplace_back();
             g = &b->groups.back();
             g->nx = p.nx;
             g->ny = p.ny;
             g->nz = p.nz;
+            for (int a = 0; a < 3; ++a) g->bc[a] = p.bc[a];
             g->fused = b->ctx[r]->fused;
             if (g->fused) {
                 g->npass = 1;  // the x pass; the y and z work runs in the yz pass
@@ -3133,6 +3143,10 @@ pft_status pft_batch_cl_steps(pft_batch* b, double* const* w_plus, double* const
     if (!(step->dt >= 0) || !(step->lambda_plus >= 0) || !(step->lambda_minus >= 0))
         return b->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
     if (step->update != 0 && step->update != 1) return b->fail(PFT_E_INVALID, "update must be 0 or 1");
+    if (step->update == 1)
+        for (const pft_ctx* c : b->ctx)
+            if (c->p.bc[0] || c->p.bc[1] || c->p.bc[2])
+                return b->fail(PFT_E_UNSUPPORTED, "batched semi-implicit steps take periodic boxes only");
     const double* const* wp = const_cast<const double* const*>(w_plus);
     const double* const* wm = const_cast<const double* const*>(w_minus);
     return b->precision == PFT_C128 ? batch_steps_t<double>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0)

@@ -156,3 +156,53 @@ def test_batch_semi_implicit_per_replica_boxes():
         assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
         assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
         ctx.close()
+
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_batch_walls_match_single_and_oracle(orc, prec):
+    """Walled replicas in a batch (grouped by grid and walls; a fused group
+    with a walled x axis among them): evaluations and graph-replayed explicit
+    steps equal those of single walled contexts, and the oracle on a subset."""
+    W = inputs.Workload
+    reps = [W("a", (24, 24, 24), (3.0, 3.0, 3.5), 30, 0.4, 15.0, C=20.0, seed=11),
+            W("b", (24, 24, 24), (3.0, 3.0, 3.5), 30, 0.4, 15.0, C=20.0, seed=12),
+            W("c", (32, 24, 40), (4.0, 3.0, 5.0), 41, 0.35, 18.0, C=20.0, seed=13),
+            W("d", (24, 24, 24), (2.5, 3.5, 3.0), 44, 0.45, 13.0, C=20.0, seed=14),
+            W("e", (16, 16, 16), (2.0, 2.0, 2.0), 25, 0.5, 14.0, C=20.0, seed=15)]
+    bcs = [(0, 0, 1), (0, 0, 0), (2, 1, 0), (0, 0, 1), (1, 0, 0)]
+    params = [B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, B.PFT_RQM4, B.PFT_DIBLOCK, 0.0,
+                       B.PFT_STORE_BOTH, bc) for w, bc in zip(reps, bcs)]
+    fields = [inputs.fields(w) for w in reps]
+    n = len(reps)
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+    pa = [torch.empty(w.n, dtype=torch.complex128, device=DEV) for w in reps]
+    pb = [torch.empty_like(t) for t in pa]
+    Q = torch.empty(n, dtype=torch.complex128, device=DEV)
+    H = torch.empty_like(Q)
+    bat.pft_batch_evaluate(wp, wm, pa, pb, Q, H)
+    log = torch.zeros((2, n, 2), dtype=torch.complex128, device=DEV)
+    bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.01, 1.0, 1.0, 5, 300, 0, 1), 2, log)
+    bat.pft_batch_sync()
+    tol = 1e-10 if prec == B.PFT_C128 else 2e-5
+    for r, w in enumerate(reps):
+        print("replica", r, w.n, bcs[r], flush=True)
+        ctx = B.Context(params[r])
+        out = ctx.evaluate(dev(fields[r][0]), dev(fields[r][1]))
+        assert np.abs(host(pa[r]) - host(out["phiA"])).max() <= 1e-13
+        assert np.abs(host(pb[r]) - host(out["phiB"])).max() <= 1e-13
+        assert abs(host(Q)[r] - host(out["Q"])[0]) <= 1e-13 * abs(host(out["Q"])[0])
+        if r in (0, 2, 4):
+            ref = orc.evaluate(orc.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, 0, False, bcs[r]), *fields[r])
+            assert np.abs(host(pa[r]) - ref["phiA"]).max() <= tol * np.abs(ref["phiA"]).max()
+            assert abs(host(Q)[r] - ref["Q"]) <= tol * abs(ref["Q"])
+            assert abs(host(H)[r] - ref["H"]) <= tol * (abs(ref["H"]) + w.C * np.prod(w.L))
+        a, b = dev(fields[r][0]), dev(fields[r][1])
+        Qt = torch.empty(1, dtype=torch.complex128, device=DEV)
+        for stepno in range(2):
+            ctx.pft_cl_step(a, b, B.pft_step(0.01, 1.0, 1.0, 5, 300 + r, stepno, 1), None, None, Qt)
+            assert abs(host(log)[stepno, r, 0] - host(Qt)[0]) <= 1e-12 * abs(host(Qt)[0])
+        assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        ctx.close()

@@ -108,9 +108,13 @@ def test_walled_rejections():
             ctx.pft_cl_step(t.clone(), t.clone(), B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1))
         assert e.value.status == B.PFT_E_UNSUPPORTED
         ctx.close()
-    with pytest.raises(B.PftError) as e:  # batches take periodic boxes
-        B.Batch([gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (1, 0, 0))])
+    # batches take walls, but their semi-implicit step takes periodic boxes only
+    bat = B.Batch([gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (1, 0, 0))])
+    t = torch.zeros((16, 16, 16), dtype=torch.complex128, device=DEV)
+    with pytest.raises(B.PftError) as e:
+        bat.pft_batch_cl_steps([t], [t.clone()], B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1), 1)
     assert e.value.status == B.PFT_E_UNSUPPORTED
+    bat.close()
     for bad, status in (((36, 16, 16), B.PFT_E_UNSUPPORTED), ((176, 16, 16), B.PFT_E_UNSUPPORTED)):
         with pytest.raises(B.PftError) as e:
             B.Context(gparams(bad, (4.0,) * 3, 10, 0.5, B.PFT_C128, (2, 0, 0)))
