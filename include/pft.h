@@ -87,9 +87,9 @@ typedef struct {
  * schedule on walled y or z axes; the semi-implicit step takes reflecting
  * walls (modes of the cosine basis) when 2N is in the axis list, not
  * absorbing ones; pft_adjoint gives dH/dw and dH/dL with walls (walled
- * modes k = pi m / L); batches take walls with the explicit step;
- * pft_debug_kgrid and the batched semi-implicit step accept periodic boxes
- * only (PFT_E_UNSUPPORTED). */
+ * modes k = pi m / L); batches take walls (their semi-implicit step as the
+ * single one); pft_debug_kgrid accepts periodic boxes only
+ * (PFT_E_UNSUPPORTED). */
 typedef enum { PFT_PERIODIC = 0, PFT_REFLECTING = 1, PFT_ABSORBING = 2 } pft_boundary;
 
 /* Where the propagators live (diblock model).
@@ -341,7 +341,9 @@ pft_status pft_batch_evaluate(pft_batch* batch, const double* const* w_plus, con
  * NULL): rows of n (Q, H) complex128 pairs, row i for the i-th step of this
  * call, up to log_rows rows.  Asynchronous; pft_batch_sync waits.  Errors:
  * PFT_E_INVALID (also update other than 0 or 1), PFT_E_UNSUPPORTED (the
- * semi-implicit step with a walled replica), PFT_E_NOMEM, PFT_E_DEVICE. */
+ * semi-implicit step with a replica it does not take: absorbing walls, or a
+ * reflecting axis whose image length has no kernel), PFT_E_NOMEM,
+ * PFT_E_DEVICE. */
 pft_status pft_batch_cl_steps(pft_batch* batch, double* const* w_plus, double* const* w_minus,
                               const pft_step* step, int32_t nsteps, double* QH_log, int64_t log_rows);
 pft_status pft_batch_sync(pft_batch* batch);

@@ -442,7 +442,7 @@ struct MirrorArgs {
     int64_t Me;
 };
 
-__global__ void k_sis_mirror(MirrorArgs a)
+__device__ __forceinline__ void sis_mirror_body(const MirrorArgs& a)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.Me; e += (int64_t)gridDim.x * blockDim.x) {
         const int ze = (int)(e % a.ne[2]);
@@ -456,8 +456,10 @@ __global__ void k_sis_mirror(MirrorArgs a)
     }
 }
 
+__global__ void k_sis_mirror(MirrorArgs a) { sis_mirror_body(a); }
+
 // w += W on the physical part of the image (W holds minus the filtered increment).
-__global__ void k_sis_unmirror(MirrorArgs a, double2* __restrict__ w, int64_t M)
+__device__ __forceinline__ void sis_unmirror_body(const MirrorArgs& a, double2* __restrict__ w, int64_t M)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
         const int z = (int)(i % a.n[2]);
@@ -466,6 +468,24 @@ __global__ void k_sis_unmirror(MirrorArgs a, double2* __restrict__ w, int64_t M)
         const double2 d = a.W[((int64_t)x * a.ne[1] + y) * a.ne[2] + z];
         w[i] = make_double2(w[i].x + d.x, w[i].y + d.y);
     }
+}
+
+__global__ void k_sis_unmirror(MirrorArgs a, double2* __restrict__ w, int64_t M) { sis_unmirror_body(a, w, M); }
+
+// Batched forms (blockIdx.y is the replica): the image arguments and the field
+// that receives the filtered increment.
+struct MirrorJob {
+    MirrorArgs m;
+    double2* w;
+    int64_t M;
+};
+
+__global__ void k_sis_mirror_batch(const MirrorJob* __restrict__ jobs) { sis_mirror_body(jobs[blockIdx.y].m); }
+
+__global__ void k_sis_unmirror_batch(const MirrorJob* __restrict__ jobs)
+{
+    const MirrorJob& j = jobs[blockIdx.y];
+    sis_unmirror_body(j.m, j.w, j.M);
 }
 
 // ------------------------------------------------------------ reverse mode --
@@ -1906,6 +1926,8 @@ static pft_status sis_prepare(pft_ctx* c);
 static SisIncArgs sis_inc_args(const pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev);
 static pft::SisArgs sis_filter_args(const pft_ctx* c, const UpdArgs& u, double2* X, double2* W, int ne_z,
                                     int64_t Me);
+static MirrorArgs sis_image(const pft_ctx* c);
+static const char* sis_walls_unsupported(const pft_params& p);
 
 // ================================================================ batches ==
 // Many independent replicas (uneven grids, contour step counts, f, chi N) run
@@ -1930,7 +1952,8 @@ struct BatchGroup {
     void* zd = nullptr;          // [dir 2][pos maxK+1][R] ZArgs (PArgs when fused)
     void* sd = nullptr;          // [dir 2][pos maxK][npass][R] SArgs
     void* jobs = nullptr;        // job tables for the small kernels
-    size_t off_sisinc = 0, off_sis = 0;  // semi-implicit step: [R] SisIncArgs, [5 passes][R] SisArgs
+    size_t off_sisinc = 0, off_sis = 0;  // semi-implicit step: [R] SisIncArgs, [5 passes][R] SisArgs,
+    size_t off_mirror = 0;               //   [R] MirrorJob (walled groups: the filter runs on the even image)
     size_t off_tab = 0, off_sum = 0, off_fin = 0, off_dens = 0, off_ham = 0, off_upd = 0;
 };
 
@@ -2118,6 +2141,7 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
     g.off_upd = place(R * sizeof(UpdArgs));
     g.off_sisinc = place(R * sizeof(SisIncArgs));
     g.off_sis = place(5 * R * sizeof(pft::SisArgs));
+    g.off_mirror = place(R * sizeof(MirrorJob));
     if (!g.jobs) PFT_BHIP(b, hipMalloc(&g.jobs, o));
     char* base = static_cast<char*>(g.jobs);
     PFT_BHIP(b, hipMemcpy(base + g.off_tab, tab.data(), R * sizeof(tab[0]), hipMemcpyHostToDevice));
@@ -2131,19 +2155,25 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
         // noise step is read from the batch's device counter
         std::vector<SisIncArgs> inc(R);
         std::vector<pft::SisArgs> fil(5 * (size_t)R);
+        std::vector<MirrorJob> mir(R);
+        const bool walls = g.bc[0] || g.bc[1] || g.bc[2];
         for (int ri = 0; ri < R; ++ri) {
             const pft_ctx* c = b->ctx[g.reps[ri]];
             inc[ri] = sis_inc_args(c, upd[ri], b->counters);
-            const pft::SisArgs f = sis_filter_args(c, upd[ri], c->sisbuf, upd[ri].wp, g.nz, c->M);
+            const MirrorArgs ma = sis_image(c);
+            mir[ri] = {ma, upd[ri].wp, c->M};
+            const pft::SisArgs f = walls ? sis_filter_args(c, upd[ri], ma.X, ma.W, ma.ne[2], ma.Me)
+                                         : sis_filter_args(c, upd[ri], c->sisbuf, upd[ri].wp, g.nz, c->M);
             for (int kind = 0; kind < 5; ++kind) {
                 pft::SisArgs& e = fil[(size_t)kind * R + ri];
                 e = f;
-                if (!pft::sis_pass_layout(kind, g.nx, g.ny, g.nz, &e))
+                if (!pft::sis_pass_layout(kind, ma.ne[0], ma.ne[1], ma.ne[2], &e))
                     return b->fail(PFT_E_UNSUPPORTED, "semi-implicit step: no kernel for this grid");
             }
         }
         PFT_BHIP(b, hipMemcpy(base + g.off_sisinc, inc.data(), R * sizeof(inc[0]), hipMemcpyHostToDevice));
         PFT_BHIP(b, hipMemcpy(base + g.off_sis, fil.data(), fil.size() * sizeof(fil[0]), hipMemcpyHostToDevice));
+        PFT_BHIP(b, hipMemcpy(base + g.off_mirror, mir.data(), R * sizeof(mir[0]), hipMemcpyHostToDevice));
     }
     return PFT_OK;
 }
@@ -2206,9 +2236,18 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool si
         hipLaunchKernelGGL(k_sis_increment_batch, dim3(grid_for((g.maxM + 3) / 4, 256), R), dim3(256), 0, s,
                            reinterpret_cast<const SisIncArgs*>(jb + g.off_sisinc));
         PFT_BHIP(b, hipGetLastError());
+        // reflecting walls: the filter runs on the even image of the increment
+        const int ne[3] = {g.bc[0] ? 2 * g.nx : g.nx, g.bc[1] ? 2 * g.ny : g.ny, g.bc[2] ? 2 * g.nz : g.nz};
+        const int64_t Me = (int64_t)ne[0] * ne[1] * ne[2];
+        const bool walls = g.bc[0] || g.bc[1] || g.bc[2];
+        const MirrorJob* mir = reinterpret_cast<const MirrorJob*>(jb + g.off_mirror);
+        if (walls) hipLaunchKernelGGL(k_sis_mirror_batch, dim3(grid_for(Me, 256), R), dim3(256), 0, s, mir);
+        PFT_BHIP(b, hipGetLastError());
         const pft::SisArgs* fil = reinterpret_cast<const pft::SisArgs*>(jb + g.off_sis);
         for (int kind = 0; kind < 5; ++kind)
-            PFT_BHIP(b, pft::launch_sis_pass_batch(kind, g.nx, g.ny, g.nz, fil + (size_t)kind * R, R, s));
+            PFT_BHIP(b, pft::launch_sis_pass_batch(kind, ne[0], ne[1], ne[2], fil + (size_t)kind * R, R, s));
+        if (walls) hipLaunchKernelGGL(k_sis_unmirror_batch, dim3(grid_for(g.maxM, 256), R), dim3(256), 0, s, mir);
+        PFT_BHIP(b, hipGetLastError());
     }
     return PFT_OK;
 }
@@ -2807,32 +2846,55 @@ static pft::SisArgs sis_filter_args(const pft_ctx* c, const UpdArgs& u, double2*
     return f;
 }
 
+// Why the semi-implicit step cannot run on this machine, or NULL: absorbing walls
+// have no diagonal linear response, and a reflecting axis of n points needs a
+// kernel for its image of 2n.
+static const char* sis_walls_unsupported(const pft_params& p)
+{
+    const int n[3] = {p.nx, p.ny, p.nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        int n1, n2, w;
+        if (p.bc[ax] == PFT_ABSORBING) return "the semi-implicit step has no linear response between absorbing walls";
+        if (p.bc[ax] == PFT_REFLECTING && !pft::axis_variant(2 * n[ax], 0, &n1, &n2, &w))
+            return "semi-implicit step between walls: no kernel for the image length of a walled axis";
+    }
+    return nullptr;
+}
+
+// The grid the filter runs on (the even image, 2n points along a reflecting
+// axis) and the image arguments over the context's buffers (sis_prepare ran).
+static MirrorArgs sis_image(const pft_ctx* c)
+{
+    const pft_params& p = c->p;
+    MirrorArgs ma{};
+    const int n[3] = {p.nx, p.ny, p.nz};
+    for (int ax = 0; ax < 3; ++ax) {
+        ma.n[ax] = n[ax];
+        ma.ne[ax] = p.bc[ax] ? 2 * n[ax] : n[ax];
+    }
+    ma.Me = (int64_t)ma.ne[0] * ma.ne[1] * ma.ne[2];
+    ma.R = c->sisbuf;
+    ma.X = c->sisext;
+    ma.W = c->sisext ? c->sisext + ma.Me : nullptr;
+    return ma;
+}
+
 static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
 {
     const pft_params& p = c->p;
     pft_status ps0 = sis_prepare(c);
     if (ps0) return ps0;
     const bool walls = p.bc[0] || p.bc[1] || p.bc[2];
-    const int n[3] = {p.nx, p.ny, p.nz};
-    int ne[3];
-    for (int ax = 0; ax < 3; ++ax) ne[ax] = p.bc[ax] ? 2 * n[ax] : n[ax];
-    const int64_t Me = (int64_t)ne[0] * ne[1] * ne[2];
+    const MirrorArgs ma = sis_image(c);
+    const int* ne = ma.ne;
+    const int64_t Me = ma.Me;
     const SisIncArgs a = sis_inc_args(c, u, nullptr);
     {
         ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
         hipLaunchKernelGGL(k_sis_increment, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
     }
     PFT_HIP(c, hipGetLastError());
-    MirrorArgs ma{};
     if (walls) {
-        ma.R = c->sisbuf;
-        ma.X = c->sisext;
-        ma.W = c->sisext + Me;
-        for (int ax = 0; ax < 3; ++ax) {
-            ma.n[ax] = n[ax];
-            ma.ne[ax] = ne[ax];
-        }
-        ma.Me = Me;
         hipLaunchKernelGGL(k_sis_mirror, dim3(grid_for(Me, 256)), dim3(256), 0, c->stream, ma);
         PFT_HIP(c, hipGetLastError());
     }
@@ -2856,16 +2918,10 @@ pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, d
     if (!(st->dt >= 0) || !(st->lambda_plus >= 0) || !(st->lambda_minus >= 0))
         return c->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
     if (st->update != 0 && st->update != 1) return c->fail(PFT_E_INVALID, "update must be 0 or 1");
-    if (st->update == 1)
-        for (int ax = 0; ax < 3; ++ax) {
-            const int nn = ax == 0 ? c->p.nx : ax == 1 ? c->p.ny : c->p.nz;
-            int n1, n2, w;
-            if (c->p.bc[ax] == PFT_ABSORBING)
-                return c->fail(PFT_E_UNSUPPORTED, "the semi-implicit step has no linear response between absorbing walls");
-            if (c->p.bc[ax] == PFT_REFLECTING && !pft::axis_variant(2 * nn, 0, &n1, &n2, &w))
-                return c->fail(PFT_E_UNSUPPORTED, "semi-implicit step between walls: no kernel for the image length %d",
-                               2 * nn);
-        }
+    if (st->update == 1) {
+        const char* why = sis_walls_unsupported(c->p);
+        if (why) return c->fail(PFT_E_UNSUPPORTED, "%s", why);
+    }
     if ((phi_a && !aligned16(phi_a)) || (phi_b && !aligned16(phi_b)) || (Q && !aligned16(Q)) || (H && !aligned16(H)))
         return c->fail(PFT_E_INVALID, "optional outputs must be 16-byte aligned");
     double* pa = phi_a ? phi_a : reinterpret_cast<double*>(c->phi);
@@ -3144,9 +3200,10 @@ pft_status pft_batch_cl_steps(pft_batch* b, double* const* w_plus, double* const
         return b->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
     if (step->update != 0 && step->update != 1) return b->fail(PFT_E_INVALID, "update must be 0 or 1");
     if (step->update == 1)
-        for (const pft_ctx* c : b->ctx)
-            if (c->p.bc[0] || c->p.bc[1] || c->p.bc[2])
-                return b->fail(PFT_E_UNSUPPORTED, "batched semi-implicit steps take periodic boxes only");
+        for (int r = 0; r < b->n; ++r) {
+            const char* why = sis_walls_unsupported(b->ctx[r]->p);
+            if (why) return b->fail(PFT_E_UNSUPPORTED, "replica %d: %s", r, why);
+        }
     const double* const* wp = const_cast<const double* const*>(w_plus);
     const double* const* wm = const_cast<const double* const*>(w_minus);
     return b->precision == PFT_C128 ? batch_steps_t<double>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0)

@@ -206,3 +206,32 @@ def test_batch_walls_match_single_and_oracle(orc, prec):
         assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
         assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
         ctx.close()
+
+
+def test_batch_semi_implicit_between_reflecting_walls():
+    """Batched semi-implicit steps with reflecting walls (the filter on each
+    replica's even image, one launch per pass over a group) equal the
+    single-context steps, periodic replicas of the same grid included."""
+    W = inputs.Workload
+    reps = [W("a", (16, 24, 20), (2.0, 3.0, 2.5), 30, 0.4, 15.0, C=20.0, seed=21),
+            W("b", (24, 24, 24), (3.0, 3.0, 3.0), 36, 0.45, 16.0, C=20.0, seed=22),
+            W("c", (24, 24, 24), (3.0, 3.0, 3.0), 28, 0.35, 14.0, C=20.0, seed=23),
+            W("d", (16, 24, 20), (2.5, 2.0, 3.0), 33, 0.5, 18.0, C=20.0, seed=24)]
+    bcs = [(1, 0, 1), (0, 0, 1), (0, 0, 0), (1, 0, 1)]
+    params = [B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, B.PFT_C128, B.PFT_RQM4, B.PFT_DIBLOCK, 0.0,
+                       B.PFT_STORE_BOTH, bc) for w, bc in zip(reps, bcs)]
+    fields = [inputs.fields(w) for w in reps]
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+    bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.2, 1.0, 0.5, 17, 60, 0, 1, 1), 2, None)
+    bat.pft_batch_sync()
+    for r, w in enumerate(reps):
+        print("replica", r, w.n, bcs[r], flush=True)
+        ctx = B.Context(params[r])
+        a, b = dev(fields[r][0]), dev(fields[r][1])
+        for stepno in range(2):
+            ctx.pft_cl_step(a, b, B.pft_step(0.2, 1.0, 0.5, 17, 60 + r, stepno, 1, 1))
+        assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        ctx.close()

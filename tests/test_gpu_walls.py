@@ -108,8 +108,8 @@ def test_walled_rejections():
             ctx.pft_cl_step(t.clone(), t.clone(), B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1))
         assert e.value.status == B.PFT_E_UNSUPPORTED
         ctx.close()
-    # batches take walls, but their semi-implicit step takes periodic boxes only
-    bat = B.Batch([gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (1, 0, 0))])
+    # batches take walls; their semi-implicit step refuses absorbing ones too
+    bat = B.Batch([gparams((16, 16, 16), (4.0,) * 3, 10, 0.5, B.PFT_C128, (0, 2, 0))])
     t = torch.zeros((16, 16, 16), dtype=torch.complex128, device=DEV)
     with pytest.raises(B.PftError) as e:
         bat.pft_batch_cl_steps([t], [t.clone()], B.pft_step(0.01, 1.0, 1.0, 0, 0, 0, 0, 1), 1)
