@@ -311,14 +311,15 @@ pft_status pft_noise_normals(uint64_t seed, uint64_t replica, uint64_t step, int
  * is one launch over all its replicas (per-replica arguments come from device
  * tables, uneven contour step counts are masked); groups run on their own
  * streams; one field step of the whole batch is captured in a HIP graph and
- * replayed.  All replicas must share precision and scheme.  This fills the
+ * replayed.  All replicas must share precision, scheme and model (Edwards
+ * replicas run one sweep each and take w_minus = NULL).  This fills the
  * GPU with small grids, which on their own cannot hide memory latency
  * (Sec. VI notes the GPU only pays off above 512-2048 plane waves). */
 typedef struct pft_batch pft_batch;
 
-/* params: n parameter sets (host memory): the diblock model with both stores,
- * periodic or walled.  Errors: PFT_E_INVALID (n < 1,
- * mixed precision/scheme, or a bad parameter set), PFT_E_UNSUPPORTED,
+/* params: n parameter sets (host memory): both stores, periodic or walled.
+ * Errors: PFT_E_INVALID (n < 1, mixed precision/scheme/model, or a bad
+ * parameter set), PFT_E_UNSUPPORTED,
  * PFT_E_NOMEM, PFT_E_DEVICE; on failure *out = NULL and nothing is kept. */
 pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_stream, pft_batch** out);
 void pft_batch_destroy(pft_batch* batch);
@@ -326,7 +327,8 @@ const char* pft_batch_last_error(const pft_batch* batch);
 
 /* One evaluation of every replica (tables, both sweeps, Q, densities, H).
  * w_plus, w_minus, phi_a, phi_b: host arrays of n device pointers (each a
- * [nx][ny][nz] complex128 field of that replica); Q, H: device arrays of n
+ * [nx][ny][nz] complex128 field of that replica; Edwards batches: omega in
+ * w_plus, w_minus NULL, phi in phi_a); Q, H: device arrays of n
  * complex128.  Errors: PFT_E_INVALID, PFT_E_DEVICE. */
 pft_status pft_batch_evaluate(pft_batch* batch, const double* const* w_plus, const double* const* w_minus,
                               double* const* phi_a, double* const* phi_b, double* Q, double* H);

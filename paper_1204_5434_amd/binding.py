@@ -382,13 +382,16 @@ class Batch:
         if st != PFT_OK:
             raise PftError(st, load().pft_batch_last_error(self._h).decode())
 
-    def _ptrs(self, tensors, name):
+    def _ptrs(self, tensors, name, optional=False):
+        if tensors is None and optional:
+            return None
         if len(tensors) != self.n:
             raise ValueError(f"{name}: expected {self.n} tensors")
         return (ctypes.c_void_p * self.n)(*[_field(t, s, name) for t, s in zip(tensors, self.shapes)])
 
     def pft_batch_evaluate(self, w_plus, w_minus, phi_a, phi_b, Q, H):
-        self._check(load().pft_batch_evaluate(self._h, self._ptrs(w_plus, "w_plus"), self._ptrs(w_minus, "w_minus"),
+        self._check(load().pft_batch_evaluate(self._h, self._ptrs(w_plus, "w_plus"),
+                                              self._ptrs(w_minus, "w_minus", optional=True),
                                               self._ptrs(phi_a, "phi_a"), self._ptrs(phi_b, "phi_b"),
                                               _field(Q, (self.n,), "Q"), _field(H, (self.n,), "H")))
 
@@ -396,7 +399,8 @@ class Batch:
         rows = 0 if log is None else log.shape[0]
         if log is not None:
             _field(log, (rows, self.n, 2), "log")
-        self._check(load().pft_batch_cl_steps(self._h, self._ptrs(w_plus, "w_plus"), self._ptrs(w_minus, "w_minus"),
+        self._check(load().pft_batch_cl_steps(self._h, self._ptrs(w_plus, "w_plus"),
+                                              self._ptrs(w_minus, "w_minus", optional=True),
                                               ctypes.byref(step), int(nsteps),
                                               None if log is None else log.data_ptr(), rows))
 

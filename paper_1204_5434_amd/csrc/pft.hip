@@ -1940,6 +1940,7 @@ namespace {
 struct BatchGroup {
     int nx = 0, ny = 0, nz = 0;
     int bc[3] = {0, 0, 0};       // walls of the group's replicas (fused groups have none on y and z)
+    int ndir = 2;                // sweeps per evaluation: 2, or 1 for the Edwards model (q-dagger = q)
     std::vector<int> reps;
     int maxK = 0;
     int64_t maxM = 0;
@@ -1961,7 +1962,7 @@ struct BatchGroup {
 
 struct pft_batch {
     int n = 0;
-    int precision = 0, scheme = 0;
+    int precision = 0, scheme = 0, model = 0;
     hipStream_t stream = nullptr;  // the caller's stream
     hipStream_t own = nullptr;     // the batch's stream: work is captured and replayed here
     std::vector<pft_ctx*> ctx;
@@ -2028,7 +2029,7 @@ pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
     std::vector<pft::ZArgs<T>> zd(g.fused ? 0 : (size_t)2 * (g.maxK + 1) * R);
     std::vector<pft::PArgs<T>> pd(g.fused ? (size_t)2 * (g.maxK + 1) * R : 0);
     std::vector<pft::SArgs<T>> sd((size_t)2 * g.maxK * g.npass * R);
-    for (int dir = 0; dir < 2; ++dir)
+    for (int dir = 0; dir < g.ndir; ++dir)
         for (int ri = 0; ri < R; ++ri) {
             pft_ctx* c = b->ctx[g.reps[ri]];
             const int K = c->K;
@@ -2089,13 +2090,15 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
     for (int ri = 0; ri < R; ++ri) {
         const int r = g.reps[ri];
         pft_ctx* c = b->ctx[r];
+        const bool ed = c->p.model == PFT_EDWARDS;  // one field omega (in wp), q-dagger = q
+        const double* wmr = ed ? nullptr : wm[r];
         TabDesc d{};
-        d.n = c->K == c->p.ns ? 2 : 4;
+        d.n = ed ? 1 : c->K == c->p.ns ? 2 : 4;
         d.blk[0] = 0; d.a[0] = c->hval[0] / 4;
         d.blk[1] = 1; d.a[1] = c->hval[0] / 4;
         d.blk[2] = 0; d.a[2] = c->hval[1] / 4;
         d.blk[3] = 1; d.a[3] = c->hval[2] / 4;
-        tab[ri] = {reinterpret_cast<const double2*>(wp[r]), reinterpret_cast<const double2*>(wm[r]), c->M, d,
+        tab[ri] = {reinterpret_cast<const double2*>(wp[r]), reinterpret_cast<const double2*>(wmr), c->M, d,
                    static_cast<cx<T>*>(c->E)};
         sum[ri] = {slice<T>(c->qs, c, c->K), c->M, c->partials};
         fin[ri] = {c->partials, kQParts, 1.0 / (double)c->M, c->scal, c->flags};
@@ -2104,14 +2107,17 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
         dens[ri] = {static_cast<const cx<T>*>(c->qs), static_cast<const cx<T>*>(c->qds), c->K, c->J, c->M, c->tau,
                     c->scal, pa, pb, Qout ? reinterpret_cast<double2*>(Qout) + r : nullptr};
         const double V = c->p.lx * c->p.ly * c->p.lz;
-        ham[ri] = {reinterpret_cast<const double2*>(wp[r]), reinterpret_cast<const double2*>(wm[r]), c->M,
-                   1.0 / c->p.chiN, c->partials + kQParts, kQParts, c->p.C, V / (double)c->M, V, c->scal,
-                   Hout ? reinterpret_cast<double2*>(Hout) + r : c->scal + 1, c->scal + 2, c->scal + 4};
+        // diblock: sum w_-^2/chiN - i w_+;  Edwards: sum (B/(2C)) omega^2
+        ham[ri] = {ed ? nullptr : reinterpret_cast<const double2*>(wp[r]),
+                   reinterpret_cast<const double2*>(ed ? wp[r] : wmr), c->M,
+                   ed ? c->p.B / (2.0 * c->p.C) : 1.0 / c->p.chiN, c->partials + kQParts, kQParts, c->p.C,
+                   V / (double)c->M, V, c->scal, Hout ? reinterpret_cast<double2*>(Hout) + r : c->scal + 1,
+                   c->scal + 2, c->scal + 4};
         UpdArgs a{};
         if (st) {
             const double dV = V / (double)c->M;
             a.wp = reinterpret_cast<double2*>(const_cast<double*>(wp[r]));
-            a.wm = reinterpret_cast<double2*>(const_cast<double*>(wm[r]));
+            a.wm = reinterpret_cast<double2*>(const_cast<double*>(wmr));
             a.phiA = pa;
             a.phiB = pb;
             a.M = c->M;
@@ -2124,6 +2130,10 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
             a.seed = st->seed;
             a.rep = st->replica + (uint64_t)r;
             a.step = 0;  // the device step counter is added at run time
+            if (ed) {
+                a.edwards = 1;
+                a.b_over_c = c->p.B / c->p.C;
+            }
         }
         upd[ri] = a;
     }
@@ -2203,7 +2213,7 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool si
         if (g.bc[2]) return pft::launch_zpass_walls_batch<T>(g.nz, g.bc[2], nlines, zd + at, R, s);
         return pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + at, R, s);
     };
-    for (int dir = 0; dir < 2; ++dir) {
+    for (int dir = 0; dir < g.ndir; ++dir) {
         PFT_BHIP(b, zlaunch(dir, 0));
         for (int p = 0; p < g.maxK; ++p) {
             for (int k = 0; k < g.npass; ++k) {
@@ -2307,7 +2317,8 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
                          int nsteps, double* log, int64_t cap)
 {
     const bool same = b->exec && b->gwp.size() == (size_t)b->n &&
-                      std::equal(b->gwp.begin(), b->gwp.end(), wp) && std::equal(b->gwm.begin(), b->gwm.end(), wm) &&
+                      std::equal(b->gwp.begin(), b->gwp.end(), wp) &&
+                      (wm ? std::equal(b->gwm.begin(), b->gwm.end(), wm) : b->gwm.empty()) &&
                       b->glog == log && b->gcap == cap && b->gst.dt == st->dt &&
                       b->gst.lambda_plus == st->lambda_plus && b->gst.lambda_minus == st->lambda_minus &&
                       b->gst.seed == st->seed && b->gst.replica == st->replica && b->gst.noise == st->noise &&
@@ -2341,7 +2352,10 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
         b->graph = graph;
         PFT_BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
         b->gwp.assign(wp, wp + b->n);
-        b->gwm.assign(wm, wm + b->n);
+        if (wm)
+            b->gwm.assign(wm, wm + b->n);
+        else
+            b->gwm.clear();
         b->glog = log;
         b->gcap = cap;
         b->gst = *st;
@@ -3085,14 +3099,17 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     *out = nullptr;
     if (!params || n < 1) return PFT_E_INVALID;
     for (int r = 1; r < n; ++r)
-        if (params[r].precision != params[0].precision || params[r].scheme != params[0].scheme) return PFT_E_INVALID;
+        if (params[r].precision != params[0].precision || params[r].scheme != params[0].scheme ||
+            params[r].model != params[0].model)
+            return PFT_E_INVALID;
     for (int r = 0; r < n; ++r)
-        if (params[r].model != PFT_DIBLOCK || params[r].storage != PFT_STORE_BOTH) return PFT_E_UNSUPPORTED;
+        if (params[r].storage != PFT_STORE_BOTH) return PFT_E_UNSUPPORTED;
     pft_batch* b = new (std::nothrow) pft_batch();
     if (!b) return PFT_E_NOMEM;
     b->n = n;
     b->precision = params[0].precision;
     b->scheme = params[0].scheme;
+    b->model = params[0].model;
     b->stream = static_cast<hipStream_t>(hip_stream);
     pft_status s = PFT_OK;
     for (int r = 0; r < n && s == PFT_OK; ++r) {
@@ -3115,6 +3132,7 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
             g->ny = p.ny;
             g->nz = p.nz;
             for (int a = 0; a < 3; ++a) g->bc[a] = p.bc[a];
+            g->ndir = p.model == PFT_EDWARDS ? 1 : 2;
             g->fused = b->ctx[r]->fused;
             if (g->fused) {
                 g->npass = 1;  // the x pass; the y and z work runs in the yz pass
@@ -3181,7 +3199,8 @@ pft_status pft_batch_evaluate(pft_batch* b, const double* const* w_plus, const d
                               double* const* phi_a, double* const* phi_b, double* Q, double* H)
 {
     if (!b) return PFT_E_INVALID;
-    if (!batch_ptrs_ok(b, w_plus, false) || !batch_ptrs_ok(b, w_minus, false) ||
+    const bool ed = b->model == PFT_EDWARDS;  // one field: w_minus is ignored and may be NULL
+    if (!batch_ptrs_ok(b, w_plus, false) || (!ed && !batch_ptrs_ok(b, w_minus, false)) ||
         !batch_ptrs_ok(b, phi_a, false) || !batch_ptrs_ok(b, phi_b, false) || !aligned16(Q) || !aligned16(H))
         return b->fail(PFT_E_INVALID, "pft_batch_evaluate: every pointer must be non-null and 16-byte aligned");
     return b->precision == PFT_C128 ? batch_evaluate_t<double>(b, w_plus, w_minus, phi_a, phi_b, Q, H)
@@ -3192,8 +3211,9 @@ pft_status pft_batch_cl_steps(pft_batch* b, double* const* w_plus, double* const
                               int32_t nsteps, double* QH_log, int64_t log_rows)
 {
     if (!b) return PFT_E_INVALID;
+    const bool ed = b->model == PFT_EDWARDS;  // one field: w_minus is ignored and may be NULL
     if (!step || nsteps < 0 || !batch_ptrs_ok(b, const_cast<const double* const*>(w_plus), false) ||
-        !batch_ptrs_ok(b, const_cast<const double* const*>(w_minus), false) || (QH_log && !aligned16(QH_log)) ||
+        (!ed && !batch_ptrs_ok(b, const_cast<const double* const*>(w_minus), false)) || (QH_log && !aligned16(QH_log)) ||
         log_rows < 0)
         return b->fail(PFT_E_INVALID, "pft_batch_cl_steps: bad arguments");
     if (!(step->dt >= 0) || !(step->lambda_plus >= 0) || !(step->lambda_minus >= 0))
@@ -3205,7 +3225,7 @@ pft_status pft_batch_cl_steps(pft_batch* b, double* const* w_plus, double* const
             if (why) return b->fail(PFT_E_UNSUPPORTED, "replica %d: %s", r, why);
         }
     const double* const* wp = const_cast<const double* const*>(w_plus);
-    const double* const* wm = const_cast<const double* const*>(w_minus);
+    const double* const* wm = ed ? nullptr : const_cast<const double* const*>(w_minus);
     return b->precision == PFT_C128 ? batch_steps_t<double>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0)
                                     : batch_steps_t<float>(b, wp, wm, step, nsteps, QH_log, QH_log ? log_rows : 0);
 }

@@ -116,10 +116,66 @@ def test_edwards_unsupported_calls():
         ctx.pft_set_concurrent_sweeps(True)
     assert e.value.status == B.PFT_E_UNSUPPORTED
     ctx.close()
-    with pytest.raises(B.PftError) as e:
-        B.Batch([p, p])
-    assert e.value.status == B.PFT_E_UNSUPPORTED
+    with pytest.raises(B.PftError) as e:  # one batch holds one model
+        B.Batch([p, B.Params(16, 16, 16, 4.0, 4.0, 4.0, 10, 0.5, 14.0, 1.0)])
+    assert e.value.status == B.PFT_E_INVALID
     bad = gparams((16, 16, 16), (4.0,) * 3, 10, 1.0, 0.0, B.PFT_C128, 0)   # B must be > 0
     with pytest.raises(B.PftError) as e:
         B.Context(bad)
     assert e.value.status == B.PFT_E_INVALID
+
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_edwards_batch_matches_single_and_oracle(orc, prec):
+    """Edwards replicas in a batch (one sweep per replica, q-dagger = q; uneven
+    grids and chain lengths; one fused group, one axis-schedule group, one
+    walled): evaluations equal single contexts and the oracle, and graph-
+    replayed explicit and semi-implicit steps equal single-context steps."""
+    specs = [((16, 16, 16), (4.0, 4.0, 4.0), 40, 2.0, 1.5, (0, 0, 0)),
+             ((24, 32, 40), (3.0, 4.0, 5.0), 25, 5.0, 0.7, (0, 0, 0)),
+             ((16, 16, 16), (3.0, 3.5, 4.0), 33, 2.0, 1.1, (0, 0, 0)),
+             ((24, 32, 40), (3.0, 4.0, 5.0), 20, 5.0, 0.7, (0, 1, 0))]
+    params = [B.Params(*n, *L, ns, 0.5, 1.0, C, prec, 0, B.PFT_EDWARDS, Bv, B.PFT_STORE_BOTH, bc)
+              for n, L, ns, C, Bv, bc in specs]
+    oms = [omega_field(s[0], 90 + i) for i, s in enumerate(specs)]
+    k = len(specs)
+    bat = B.Batch(params)
+    g = [dev(o) for o in oms]
+    pa = [torch.empty(s[0], dtype=torch.complex128, device=DEV) for s in specs]
+    pb = [torch.empty_like(t) for t in pa]
+    Q = torch.empty(k, dtype=torch.complex128, device=DEV)
+    H = torch.empty_like(Q)
+    bat.pft_batch_evaluate(g, None, pa, pb, Q, H)
+    bat.pft_batch_sync()
+    tol = 1e-10 if prec == B.PFT_C128 else 2e-5
+    for r, (n, L, ns, C, Bv, bc) in enumerate(specs):
+        print("replica", r, n, ns, bc, flush=True)
+        ctx = B.Context(params[r])
+        out = ctx.evaluate(dev(oms[r]))
+        assert np.abs(host(pa[r]) - host(out["phiA"])).max() <= 1e-13
+        assert abs(host(Q)[r] - host(out["Q"])[0]) <= 1e-13 * abs(host(out["Q"])[0])
+        assert abs(host(H)[r] - host(out["H"])[0]) <= 1e-12 * (abs(host(out["H"])[0]) + C * np.prod(L))
+        ref = orc.edwards_evaluate(orc.Params(*n, *L, ns, 0.5, 1.0, C, 0, False, bc), Bv, oms[r])
+        assert np.abs(host(pa[r]) - ref["phi"]).max() <= tol * np.abs(ref["phi"]).max()
+        assert abs(host(Q)[r] - ref["Q"]) <= tol * abs(ref["Q"])
+        ctx.close()
+    # two explicit steps, then one semi-implicit step (periodic replicas only)
+    per = [r for r, s in enumerate(specs) if not any(s[5])]
+    bat.pft_batch_cl_steps(g, None, B.pft_step(0.01, 1.0, 1.0, 8, 500, 0, 1), 2, None)
+    bat2 = B.Batch([params[r] for r in per])
+    g2 = [dev(oms[r]) for r in per]
+    bat2.pft_batch_cl_steps(g2, None, B.pft_step(0.3, 1.0, 1.0, 8, 700, 0, 1, 1), 1, None)
+    bat.pft_batch_sync()
+    bat2.pft_batch_sync()
+    for r in range(k):
+        ctx = B.Context(params[r])
+        a = dev(oms[r])
+        for stepno in range(2):
+            ctx.pft_cl_step(a, None, B.pft_step(0.01, 1.0, 1.0, 8, 500 + r, stepno, 1))
+        assert np.abs(host(g[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        if r in per:
+            i = per.index(r)
+            b = dev(oms[r])
+            ctx.pft_cl_step(b, None, B.pft_step(0.3, 1.0, 1.0, 8, 700 + i, 0, 1, 1))
+            assert np.abs(host(g2[i]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        ctx.close()
