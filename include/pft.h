@@ -325,7 +325,8 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
 void pft_batch_destroy(pft_batch* batch);
 const char* pft_batch_last_error(const pft_batch* batch);
 
-/* One evaluation of every replica (tables, both sweeps, Q, densities, H).
+/* One evaluation of every replica (tables, both sweeps or the Edwards model's
+ * one, Q, densities, H).
  * w_plus, w_minus, phi_a, phi_b: host arrays of n device pointers (each a
  * [nx][ny][nz] complex128 field of that replica; Edwards batches: omega in
  * w_plus, w_minus NULL, phi in phi_a); Q, H: device arrays of n
