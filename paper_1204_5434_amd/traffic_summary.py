@@ -7,9 +7,9 @@ reads for the library's plain copy kernel (``k_copy_probe``) moving a known
 the hash of that kernel's sources, to ``profiles/lam128_hbm_traffic.txt``,
 the file ``bench.py`` reads for ``roofline.traffic``.
 
-Usage: python -m paper_1204_5434_amd.traffic_summary [counter-run-dir]
-(the directory holding ``pmc_FETCH_SIZE/`` and ``pmc_WRITE_SIZE/``; default
-``gpurun_out``).  Prints the table rows of every kernel as well.
+Usage: python -m paper_1204_5434_amd.traffic_summary COUNTER_RUN_DIR
+(the directory holding the two runs' ``pmc_FETCH_SIZE/`` and ``pmc_WRITE_SIZE/``
+output).  Prints the table rows of every kernel as well.
 """
 import collections
 import csv
@@ -74,8 +74,9 @@ def summarize(base: str):
 
 
 def main(argv):
-    base = argv[1] if len(argv) > 1 else os.path.join(ROOT, "gpurun_out")
-    txt, rows = summarize(base)
+    if len(argv) != 2:
+        raise SystemExit("usage: python -m paper_1204_5434_amd.traffic_summary COUNTER_RUN_DIR")
+    txt, rows = summarize(argv[1])
     with open(os.path.join(ROOT, "profiles", "lam128_hbm_traffic.txt"), "w") as fh:
         fh.write("\n".join(txt) + "\n")
     print("\n".join(txt))
