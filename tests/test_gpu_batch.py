@@ -235,3 +235,50 @@ def test_batch_semi_implicit_between_reflecting_walls():
         assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
         assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
         ctx.close()
+
+
+@pytest.mark.parametrize("model", [B.PFT_DIBLOCK, B.PFT_EDWARDS])
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_batch_plain_split_matches_single(model, prec):
+    """The plain split step (two strided passes per step) in batches, periodic
+    and walled groups, diblock and Edwards: evaluations and graph-replayed
+    explicit steps equal single contexts."""
+    specs = [((24, 24, 24), (3.0, 3.0, 3.0), 30, (0, 0, 0)),
+             ((16, 24, 20), (2.0, 3.0, 2.5), 21, (1, 0, 2)),
+             ((24, 24, 24), (2.5, 3.5, 3.0), 37, (0, 0, 0))]
+    params = [B.Params(*n, *L, ns, 0.4, 15.0, 10.0, prec, B.PFT_SPLIT2, model,
+                       1.2 if model == B.PFT_EDWARDS else 0.0, B.PFT_STORE_BOTH, bc) for n, L, ns, bc in specs]
+    rng = np.random.default_rng(31)
+    fl = [(0.3 * rng.standard_normal(s[0]) + 0.05j * rng.standard_normal(s[0]),
+           0.4 * rng.standard_normal(s[0]) + 0.05j * rng.standard_normal(s[0])) for s in specs]
+    ed = model == B.PFT_EDWARDS
+    k = len(specs)
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fl]
+    wm = None if ed else [dev(f[1]) for f in fl]
+    pa = [torch.empty(s[0], dtype=torch.complex128, device=DEV) for s in specs]
+    pb = [torch.empty_like(t) for t in pa]
+    Q = torch.empty(k, dtype=torch.complex128, device=DEV)
+    H = torch.empty_like(Q)
+    bat.pft_batch_evaluate(wp, wm, pa, pb, Q, H)
+    bat.pft_batch_sync()
+    for r in range(k):
+        ctx = B.Context(params[r])
+        out = ctx.evaluate(dev(fl[r][0]), None if ed else dev(fl[r][1]))
+        assert np.abs(host(pa[r]) - host(out["phiA"])).max() <= 1e-13
+        assert abs(host(Q)[r] - host(out["Q"])[0]) <= 1e-13 * abs(host(out["Q"])[0])
+        assert abs(host(H)[r] - host(out["H"])[0]) <= 1e-12 * (abs(host(out["H"])[0]) + 10.0 * np.prod(specs[r][1]))
+        ctx.close()
+    bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.01, 1.0, 1.0, 3, 80, 0, 1), 2, None)
+    bat.pft_batch_sync()
+    for r in range(k):
+        print("replica", r, specs[r][0], specs[r][3], flush=True)
+        ctx = B.Context(params[r])
+        a = dev(fl[r][0])
+        b = None if ed else dev(fl[r][1])
+        for stepno in range(2):
+            ctx.pft_cl_step(a, b, B.pft_step(0.01, 1.0, 1.0, 3, 80 + r, stepno, 1))
+        assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        if not ed:
+            assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        ctx.close()
