@@ -390,6 +390,20 @@ def batched_gain(binding, inputs, count: int, steps: int):
     ms = t0.elapsed_time(t1) / steps
     out["batched_c64_graph_semi_implicit"] = {"ms_per_field_step": ms, "value": site_steps / (ms * 1e-3)}
     bat.close()
+    # Edwards replicas on the same grids and chain lengths (B = 1): one sweep each
+    ed_params = [binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, binding.PFT_C64, binding.PFT_RQM4,
+                                binding.PFT_EDWARDS, 1.0) for w in reps]
+    bat = binding.Batch(ed_params)
+    bat.pft_batch_cl_steps(wp, None, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 0, 1), 1)  # capture
+    torch.cuda.synchronize()
+    t0.record()
+    bat.pft_batch_cl_steps(wp, None, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 1, 1), steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    out["batched_edwards_c64_graph"] = {"ms_per_field_step": ms, "site_steps_per_field_step": site_steps / 2,
+                                        "value": site_steps / 2 / (ms * 1e-3)}
+    bat.close()
     del wp, wm
     # one at a time, complex128, plain launches
     wp = [torch.from_numpy(f[0]).to("cuda") for f in fields]
