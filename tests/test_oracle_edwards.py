@@ -135,3 +135,25 @@ def test_update_noise_stream_and_scale(orc):
     assert np.abs((noisy - det) - s * xi).max() < 1e-14
     F = orc.edwards_force(p, B, omega, phi)
     assert np.abs(det - (omega - lam * dt * F)).max() < 1e-15
+
+
+def test_em_drift_is_first_order_descent_of_H(orc):
+    """One noise-free step of Eq. (9) on the Edwards field changes H by
+    -lam dt C dV sum F^2 to first order (dH/domega = C dV F under the plain
+    split, pinned above by central differences); the relative residual halves
+    with dt.  A flipped drift or dt in place of lam dt fails."""
+    p = P(orc, n=(6, 4, 8), L=(3.0, 2.0, 4.0), ns=16, C=2.0, scheme=1)
+    B, lam = 1.3, 0.6
+    omega = rand_omega(p.shape, 51)
+    base = orc.edwards_evaluate(p, B, omega)
+    F = orc.edwards_force(p, B, omega, base["phi"])
+    dV = p.volume / p.M
+    rel = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        new = orc.edwards_em_update(p, B, omega, base["phi"], dt, lam)
+        dH = orc.edwards_evaluate(p, B, new)["H"] - base["H"]
+        pred = -lam * dt * p.C * dV * np.sum(F * F)
+        rel.append((dH - pred) / pred)
+    assert abs(rel[-1]) < 2e-2, rel
+    for a, b in zip(rel, rel[1:]):
+        assert 1.8 < abs(a / b) < 2.2, rel
