@@ -458,6 +458,25 @@ __device__ __forceinline__ void sis_mirror_body(const MirrorArgs& a)
 
 __global__ void k_sis_mirror(MirrorArgs a) { sis_mirror_body(a); }
 
+// |k|^2 = (2 pi m / Le)^2 per axis in natural order (m = j, or j - ne above
+// ne / 2), Le the period the filter sees (2L along a reflecting axis): row
+// blockIdx.x of k2.  The same operations, in the same order, as the host
+// table of the context's semi-implicit step.
+struct K2Rows {
+    int ne[3];
+    double Le[3];
+};
+
+__global__ void k_fill_k2(double* __restrict__ k2, int pitch, K2Rows r)
+{
+    const int ax = blockIdx.x;
+    for (int j = threadIdx.x; j < r.ne[ax]; j += blockDim.x) {
+        const int m = (j <= r.ne[ax] / 2) ? j : j - r.ne[ax];
+        const double k = kTwoPi * m / r.Le[ax];
+        k2[(size_t)ax * pitch + j] = k * k;
+    }
+}
+
 // w += W on the physical part of the image (W holds minus the filtered increment).
 __device__ __forceinline__ void sis_unmirror_body(const MirrorArgs& a, double2* __restrict__ w, int64_t M)
 {
@@ -815,7 +834,7 @@ constexpr int kRing = 4;  // device slots per direction of host staging
 struct pft_ctx {
     pft_params p{};
     hipStream_t stream = nullptr;
-    int device = 0;
+    int device = 0;               // the device current at creation
     int64_t M = 0;
     int K = 0, J = 0;
     std::vector<double> h;
@@ -1923,10 +1942,22 @@ void free_all(pft_ctx* c)
 
 // The semi-implicit step (defined with the field steps below).
 static pft_status sis_prepare(pft_ctx* c);
-static SisIncArgs sis_inc_args(const pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev);
-static pft::SisArgs sis_filter_args(const pft_ctx* c, const UpdArgs& u, double2* X, double2* W, int ne_z,
+static pft_status sis_upload_k2(pft_ctx* c);
+// Work memory of one semi-implicit step: the increment R (M sites), between
+// reflecting walls its even image X and the image's update W (Me sites each),
+// and |k|^2 per axis (3 rows of `pitch` doubles, natural order).
+struct SisBufs {
+    double2* R = nullptr;
+    double2* X = nullptr;
+    double2* W = nullptr;
+    const double* k2 = nullptr;
+    int pitch = 0;
+};
+static SisBufs ctx_sis_bufs(const pft_ctx* c);
+static SisIncArgs sis_inc_args(const pft_ctx* c, const SisBufs& sb, const UpdArgs& u, const uint64_t* step_dev);
+static pft::SisArgs sis_filter_args(const SisBufs& sb, const UpdArgs& u, double2* X, double2* W, int ne_z,
                                     int64_t Me);
-static MirrorArgs sis_image(const pft_ctx* c);
+static MirrorArgs sis_image(const pft_ctx* c, const SisBufs& sb);
 static const char* sis_walls_unsupported(const pft_params& p);
 
 // ================================================================ batches ==
@@ -1952,7 +1983,7 @@ struct BatchGroup {
     hipEvent_t done = nullptr;
     void* zd = nullptr;          // [dir 2][pos maxK+1][R] ZArgs (PArgs when fused)
     void* sd = nullptr;          // [dir 2][pos maxK][npass][R] SArgs
-    void* jobs = nullptr;        // job tables for the small kernels
+    void* jobs[2] = {nullptr, nullptr};  // job tables of the small kernels: [0] evaluations, [1] the captured field step
     size_t off_sisinc = 0, off_sis = 0;  // semi-implicit step: [R] SisIncArgs, [5 passes][R] SisArgs,
     size_t off_mirror = 0;               //   [R] MirrorJob (walled groups: the filter runs on the even image)
     size_t off_tab = 0, off_sum = 0, off_fin = 0, off_dens = 0, off_ham = 0, off_upd = 0;
@@ -1974,6 +2005,7 @@ struct pft_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const double*> gwp, gwm;  // field pointers baked into the graph
+    std::vector<const void*> ekey;        // pointers held by the evaluation job tables
     pft_step gst{};
     double* glog = nullptr;
     int64_t gcap = 0;
@@ -2009,7 +2041,8 @@ void batch_free(pft_batch* b)
         if (g.done) (void)hipEventDestroy(g.done);
         if (g.zd) (void)hipFree(g.zd);
         if (g.sd) (void)hipFree(g.sd);
-        if (g.jobs) (void)hipFree(g.jobs);
+        for (void* j : g.jobs)
+            if (j) (void)hipFree(j);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->in) (void)hipEventDestroy(b->in);
@@ -2076,7 +2109,7 @@ pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
 // Job tables of the small kernels of one group for the given field pointers
 // and outputs (phi / Q / H default to each context's internal buffers).
 template <typename T>
-pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp, const double* const* wm,
+pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, int slot, const double* const* wp, const double* const* wm,
                             double* const* phia, double* const* phib, double* Qout, double* Hout, const pft_step* st)
 {
     const int R = (int)g.reps.size();
@@ -2152,8 +2185,8 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
     g.off_sisinc = place(R * sizeof(SisIncArgs));
     g.off_sis = place(5 * R * sizeof(pft::SisArgs));
     g.off_mirror = place(R * sizeof(MirrorJob));
-    if (!g.jobs) PFT_BHIP(b, hipMalloc(&g.jobs, o));
-    char* base = static_cast<char*>(g.jobs);
+    if (!g.jobs[slot]) PFT_BHIP(b, hipMalloc(&g.jobs[slot], o));
+    char* base = static_cast<char*>(g.jobs[slot]);
     PFT_BHIP(b, hipMemcpy(base + g.off_tab, tab.data(), R * sizeof(tab[0]), hipMemcpyHostToDevice));
     PFT_BHIP(b, hipMemcpy(base + g.off_sum, sum.data(), R * sizeof(sum[0]), hipMemcpyHostToDevice));
     PFT_BHIP(b, hipMemcpy(base + g.off_fin, fin.data(), R * sizeof(fin[0]), hipMemcpyHostToDevice));
@@ -2169,11 +2202,12 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
         const bool walls = g.bc[0] || g.bc[1] || g.bc[2];
         for (int ri = 0; ri < R; ++ri) {
             const pft_ctx* c = b->ctx[g.reps[ri]];
-            inc[ri] = sis_inc_args(c, upd[ri], b->counters);
-            const MirrorArgs ma = sis_image(c);
+            const SisBufs sb = ctx_sis_bufs(c);
+            inc[ri] = sis_inc_args(c, sb, upd[ri], b->counters);
+            const MirrorArgs ma = sis_image(c, sb);
             mir[ri] = {ma, upd[ri].wp, c->M};
-            const pft::SisArgs f = walls ? sis_filter_args(c, upd[ri], ma.X, ma.W, ma.ne[2], ma.Me)
-                                         : sis_filter_args(c, upd[ri], c->sisbuf, upd[ri].wp, g.nz, c->M);
+            const pft::SisArgs f = walls ? sis_filter_args(sb, upd[ri], ma.X, ma.W, ma.ne[2], ma.Me)
+                                         : sis_filter_args(sb, upd[ri], sb.R, upd[ri].wp, g.nz, c->M);
             for (int kind = 0; kind < 5; ++kind) {
                 pft::SisArgs& e = fil[(size_t)kind * R + ri];
                 e = f;
@@ -2191,11 +2225,11 @@ pft_status batch_build_jobs(pft_batch* b, BatchGroup& g, const double* const* wp
 // Enqueue one evaluation (and, if update, the field step: explicit, or
 // semi-implicit when sis) of one group on its stream.
 template <typename T>
-pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool sis)
+pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, int slot, bool update, bool sis)
 {
     const int R = (int)g.reps.size();
     hipStream_t s = g.s;
-    char* jb = static_cast<char*>(g.jobs);
+    char* jb = static_cast<char*>(g.jobs[slot]);
     const int64_t nlines = (int64_t)g.nx * g.ny;
     hipLaunchKernelGGL((k_tables_batch<T>), dim3(grid_for(g.maxM, 256), R), dim3(256), 0, s,
                        reinterpret_cast<const TabJob<T>*>(jb + g.off_tab));
@@ -2264,12 +2298,12 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, bool update, bool si
 
 // Fork the group streams off the batch stream, enqueue every group, join.
 template <typename T>
-pft_status batch_enqueue(pft_batch* b, bool update, bool sis, const double2* logbuf, int64_t cap)
+pft_status batch_enqueue(pft_batch* b, int slot, bool update, bool sis, const double2* logbuf, int64_t cap)
 {
     PFT_BHIP(b, hipEventRecord(b->fork, b->own));
     for (BatchGroup& g : b->groups) {
         PFT_BHIP(b, hipStreamWaitEvent(g.s, b->fork, 0));
-        pft_status st = batch_enqueue_group<T>(b, g, update, sis);
+        pft_status st = batch_enqueue_group<T>(b, g, slot, update, sis);
         if (st) return st;
         PFT_BHIP(b, hipEventRecord(g.done, g.s));
         PFT_BHIP(b, hipStreamWaitEvent(b->own, g.done, 0));
@@ -2294,18 +2328,45 @@ pft_status batch_setup_t(pft_batch* b)
     return PFT_OK;
 }
 
+// Wait until nothing queued on the batch's own and group streams remains:
+// the job tables are rewritten with host copies, which are not ordered after
+// that work, and a graph still replaying must not be destroyed.
+pft_status batch_quiesce(pft_batch* b)
+{
+    PFT_BHIP(b, hipStreamSynchronize(b->own));
+    for (BatchGroup& g : b->groups) PFT_BHIP(b, hipStreamSynchronize(g.s));
+    return PFT_OK;
+}
+
 template <typename T>
 pft_status batch_evaluate_t(pft_batch* b, const double* const* wp, const double* const* wm, double* const* pa,
                             double* const* pb, double* Q, double* H)
 {
-    for (BatchGroup& g : b->groups) {
-        pft_status s = batch_build_jobs<T>(b, g, wp, wm, pa, pb, Q, H, nullptr);
-        if (s) return s;
+    // the evaluation tables (slot 0) are rebuilt only when a pointer changes;
+    // the captured field step keeps its own tables (slot 1)
+    std::vector<const void*> key;
+    key.reserve(4 * (size_t)b->n + 2);
+    for (int r = 0; r < b->n; ++r) {
+        key.push_back(wp[r]);
+        key.push_back(wm ? wm[r] : nullptr);
+        key.push_back(pa[r]);
+        key.push_back(pb[r]);
     }
-    b->gwp.clear();  // the jobs no longer match a captured graph
+    key.push_back(Q);
+    key.push_back(H);
+    if (key != b->ekey) {
+        b->ekey.clear();
+        pft_status s = batch_quiesce(b);
+        if (s) return s;
+        for (BatchGroup& g : b->groups) {
+            s = batch_build_jobs<T>(b, g, 0, wp, wm, pa, pb, Q, H, nullptr);
+            if (s) return s;
+        }
+        b->ekey = std::move(key);
+    }
     PFT_BHIP(b, hipEventRecord(b->in, b->stream));
     PFT_BHIP(b, hipStreamWaitEvent(b->own, b->in, 0));
-    pft_status s = batch_enqueue<T>(b, false, false, nullptr, 0);
+    pft_status s = batch_enqueue<T>(b, 0, false, false, nullptr, 0);
     if (s) return s;
     PFT_BHIP(b, hipEventRecord(b->out, b->own));
     PFT_BHIP(b, hipStreamWaitEvent(b->stream, b->out, 0));
@@ -2324,6 +2385,9 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
                       b->gst.seed == st->seed && b->gst.replica == st->replica && b->gst.noise == st->noise &&
                       b->gst.update == st->update;
     if (!same) {
+        b->gwp.clear();
+        pft_status qs = batch_quiesce(b);  // a replay may still read the tables
+        if (qs) return qs;
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
@@ -2334,14 +2398,14 @@ pft_status batch_steps_t(pft_batch* b, const double* const* wp, const double* co
                 if (ps) return b->fail(ps, "replica %d: %s", r, b->ctx[r]->err.c_str());
             }
         for (BatchGroup& g : b->groups) {
-            pft_status s = batch_build_jobs<T>(b, g, wp, wm, nullptr, nullptr, nullptr, nullptr, st);
+            pft_status s = batch_build_jobs<T>(b, g, 1, wp, wm, nullptr, nullptr, nullptr, nullptr, st);
             if (s) return s;
         }
         std::vector<LogJob> lj(b->n);
         for (int r = 0; r < b->n; ++r) lj[r] = {b->ctx[r]->scal, b->ctx[r]->scal + 1};
         PFT_BHIP(b, hipMemcpy(b->logj, lj.data(), lj.size() * sizeof(LogJob), hipMemcpyHostToDevice));
         PFT_BHIP(b, hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
-        pft_status s = batch_enqueue<T>(b, true, st->update == 1, reinterpret_cast<const double2*>(log), cap);
+        pft_status s = batch_enqueue<T>(b, 1, true, st->update == 1, reinterpret_cast<const double2*>(log), cap);
         hipGraph_t graph = nullptr;
         const hipError_t ec = hipStreamEndCapture(b->own, &graph);
         if (s) {
@@ -2563,6 +2627,11 @@ static pft_status create_ctx(const pft_params* params, void* hip_stream, bool du
     pft_ctx* c = new (std::nothrow) pft_ctx();
     if (!c) return PFT_E_NOMEM;
     c->p = p;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return PFT_E_DEVICE;
+    }
     c->var[0] = tuned_variant(p.precision, p.nx, 1);
     c->var[1] = tuned_variant(p.precision, p.ny, 1);
     c->var[2] = tuned_variant(p.precision, p.nz, 0);
@@ -2758,6 +2827,32 @@ pft_status pft_evaluate_graph(pft_ctx* c, const double* wp, const double* wm, do
     return PFT_OK;
 }
 
+pft_status pft_set_box(pft_ctx* c, double lx, double ly, double lz)
+{
+    if (!c) return PFT_E_INVALID;
+    if (!(lx > 0) || !(ly > 0) || !(lz > 0) || !std::isfinite(lx) || !std::isfinite(ly) || !std::isfinite(lz))
+        return c->fail(PFT_E_INVALID, "box edges must be finite and > 0");
+    // queued work may still read the tables rewritten below
+    PFT_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->s2) PFT_HIP(c, hipStreamSynchronize(c->s2));
+    if (c->gs) PFT_HIP(c, hipStreamSynchronize(c->gs));
+    if (c->cs) PFT_HIP(c, hipStreamSynchronize(c->cs));
+    c->p.lx = lx;
+    c->p.ly = ly;
+    c->p.lz = lz;
+    c->propagated = false;
+    const bool dbl = c->p.precision == PFT_C128;
+    for (int hd = 0; hd < 3; ++hd) {
+        const double hv = c->hval[hd] > 0 ? c->hval[hd] : c->hval[0];
+        const pft_status s = dbl ? upload_factors<double>(c, hd, hv) : upload_factors<float>(c, hd, hv);
+        if (s) return s;
+    }
+    const pft_status s = dbl ? upload_second_derivative<double>(c) : upload_second_derivative<float>(c);
+    if (s) return s;
+    if (c->k2) return sis_upload_k2(c);
+    return PFT_OK;
+}
+
 pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, double* H, double* hint)
 {
     if (!c) return PFT_E_INVALID;
@@ -2770,6 +2865,26 @@ pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, doubl
 // Semi-implicit step (Eqs. (10)-(11)) from the explicit step's arguments: the
 // local increment kernel, then the reciprocal-space filter of the w_+ (or
 // omega) increment in five axis passes over a work array.
+// |k|^2 per axis for the semi-implicit filter (walled axes: the modes of the
+// even image, period 2L), written into the allocated c->k2.
+static pft_status sis_upload_k2(pft_ctx* c)
+{
+    const pft_params& p = c->p;
+    const int n[3] = {p.nx, p.ny, p.nz};
+    const double L[3] = {p.lx, p.ly, p.lz};
+    std::vector<double> k2(3 * (size_t)c->maxN, 0.0);
+    for (int ax = 0; ax < 3; ++ax) {
+        const int ne = p.bc[ax] ? 2 * n[ax] : n[ax];
+        for (int j = 0; j < ne; ++j) {
+            const int m = (j <= ne / 2) ? j : j - ne;
+            const double k = kTwoPi * m / ((double)ne / n[ax] * L[ax]);
+            k2[(size_t)ax * c->maxN + j] = k * k;
+        }
+    }
+    PFT_HIP(c, hipMemcpy(c->k2, k2.data(), k2.size() * sizeof(double), hipMemcpyHostToDevice));
+    return PFT_OK;
+}
+
 // Buffers of the semi-implicit step (allocated on first use; batches allocate
 // them before capturing their graphs).
 static pft_status sis_prepare(pft_ctx* c)
@@ -2796,34 +2911,42 @@ static pft_status sis_prepare(pft_ctx* c)
         }
     }
     if (!c->k2) {
-        std::vector<double> k2(3 * (size_t)c->maxN, 0.0);
-        const double L[3] = {p.lx, p.ly, p.lz};
-        for (int ax = 0; ax < 3; ++ax)
-            for (int j = 0; j < ne[ax]; ++j) {
-                const int m = (j <= ne[ax] / 2) ? j : j - ne[ax];
-                const double k = kTwoPi * m / ((double)ne[ax] / n[ax] * L[ax]);
-                k2[(size_t)ax * c->maxN + j] = k * k;
-            }
-        if (hipMalloc((void**)&c->k2, k2.size() * sizeof(double)) != hipSuccess) {
+        if (hipMalloc((void**)&c->k2, 3 * (size_t)c->maxN * sizeof(double)) != hipSuccess) {
             (void)hipGetLastError();
             c->k2 = nullptr;
             return c->fail(PFT_E_NOMEM, "semi-implicit step: cannot allocate the k tables");
         }
-        PFT_HIP(c, hipMemcpy(c->k2, k2.data(), k2.size() * sizeof(double), hipMemcpyHostToDevice));
+        return sis_upload_k2(c);
     }
     return PFT_OK;
 }
 
 // Arguments of the local increment kernel of one context; step_dev: device
 // step counter added to the noise step (batches), or NULL.
-static SisIncArgs sis_inc_args(const pft_ctx* c, const UpdArgs& u, const uint64_t* step_dev)
+static SisBufs ctx_sis_bufs(const pft_ctx* c)
+{
+    SisBufs sb;
+    sb.R = c->sisbuf;
+    sb.X = c->sisext;
+    if (c->sisext) {
+        const int n[3] = {c->p.nx, c->p.ny, c->p.nz};
+        int64_t Me = 1;
+        for (int ax = 0; ax < 3; ++ax) Me *= c->p.bc[ax] ? 2 * n[ax] : n[ax];
+        sb.W = c->sisext + Me;
+    }
+    sb.k2 = c->k2;
+    sb.pitch = c->maxN;
+    return sb;
+}
+
+static SisIncArgs sis_inc_args(const pft_ctx* c, const SisBufs& sb, const UpdArgs& u, const uint64_t* step_dev)
 {
     SisIncArgs a{};
     a.wp = u.wp;
     a.wm = u.wm;
     a.phiA = u.phiA;
     a.phiB = u.phiB;
-    a.R = c->sisbuf;
+    a.R = sb.R;
     a.M = c->M;
     a.two_over_chiN = u.two_over_chiN;
     a.ap = u.dtp;
@@ -2843,15 +2966,15 @@ static SisIncArgs sis_inc_args(const pft_ctx* c, const UpdArgs& u, const uint64_
 
 // Arguments of the reciprocal-space filter passes over X (Me sites, last
 // axis ne_z long), subtracting from W.
-static pft::SisArgs sis_filter_args(const pft_ctx* c, const UpdArgs& u, double2* X, double2* W, int ne_z,
+static pft::SisArgs sis_filter_args(const SisBufs& sb, const UpdArgs& u, double2* X, double2* W, int ne_z,
                                     int64_t Me)
 {
     pft::SisArgs f{};
     f.X = reinterpret_cast<cx<double>*>(X);
     f.W = reinterpret_cast<cx<double>*>(W);
-    f.k2x = c->k2;
-    f.k2y = c->k2 + c->maxN;
-    f.k2z = c->k2 + 2 * (size_t)c->maxN;
+    f.k2x = sb.k2;
+    f.k2y = sb.k2 + sb.pitch;
+    f.k2z = sb.k2 + 2 * (size_t)sb.pitch;
     f.nz = ne_z;
     f.a = u.dtp;
     f.g0 = u.edwards ? u.b_over_c : 0.0;
@@ -2877,7 +3000,7 @@ static const char* sis_walls_unsupported(const pft_params& p)
 
 // The grid the filter runs on (the even image, 2n points along a reflecting
 // axis) and the image arguments over the context's buffers (sis_prepare ran).
-static MirrorArgs sis_image(const pft_ctx* c)
+static MirrorArgs sis_image(const pft_ctx* c, const SisBufs& sb)
 {
     const pft_params& p = c->p;
     MirrorArgs ma{};
@@ -2887,22 +3010,38 @@ static MirrorArgs sis_image(const pft_ctx* c)
         ma.ne[ax] = p.bc[ax] ? 2 * n[ax] : n[ax];
     }
     ma.Me = (int64_t)ma.ne[0] * ma.ne[1] * ma.ne[2];
-    ma.R = c->sisbuf;
-    ma.X = c->sisext;
-    ma.W = c->sisext ? c->sisext + ma.Me : nullptr;
+    ma.R = sb.R;
+    ma.X = sb.X;
+    ma.W = sb.W;
     return ma;
 }
 
-static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
+// ext: work memory in place of the context's (whose buffers are allocated on
+// first use when ext is NULL); its |k|^2 rows are filled here, on the stream.
+static pft_status sis_step(pft_ctx* c, const UpdArgs& u, const SisBufs* ext = nullptr)
 {
     const pft_params& p = c->p;
-    pft_status ps0 = sis_prepare(c);
-    if (ps0) return ps0;
+    if (!ext) {
+        pft_status ps0 = sis_prepare(c);
+        if (ps0) return ps0;
+    }
+    const SisBufs sb = ext ? *ext : ctx_sis_bufs(c);
     const bool walls = p.bc[0] || p.bc[1] || p.bc[2];
-    const MirrorArgs ma = sis_image(c);
+    const MirrorArgs ma = sis_image(c, sb);
     const int* ne = ma.ne;
     const int64_t Me = ma.Me;
-    const SisIncArgs a = sis_inc_args(c, u, nullptr);
+    if (ext) {
+        const int n[3] = {p.nx, p.ny, p.nz};
+        const double L[3] = {p.lx, p.ly, p.lz};
+        K2Rows kr{};
+        for (int ax = 0; ax < 3; ++ax) {
+            kr.ne[ax] = ne[ax];
+            kr.Le[ax] = (double)ne[ax] / n[ax] * L[ax];
+        }
+        hipLaunchKernelGGL(k_fill_k2, dim3(3), dim3(256), 0, c->stream, const_cast<double*>(sb.k2), sb.pitch, kr);
+        PFT_HIP(c, hipGetLastError());
+    }
+    const SisIncArgs a = sis_inc_args(c, sb, u, nullptr);
     {
         ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
         hipLaunchKernelGGL(k_sis_increment, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
@@ -2912,7 +3051,7 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
         hipLaunchKernelGGL(k_sis_mirror, dim3(grid_for(Me, 256)), dim3(256), 0, c->stream, ma);
         PFT_HIP(c, hipGetLastError());
     }
-    const pft::SisArgs f = sis_filter_args(c, u, walls ? ma.X : c->sisbuf, walls ? ma.W : u.wp, ne[2], Me);
+    const pft::SisArgs f = sis_filter_args(sb, u, walls ? ma.X : sb.R, walls ? ma.W : u.wp, ne[2], Me);
     for (int kind = 0; kind < 5; ++kind) {
         ProfScope ps(c, PFT_K_REDUCE, (kind == 4 ? 3.0 : 2.0) * sizeof(double2) * (double)Me);
         PFT_HIP(c, pft::launch_sis_pass(kind, ne[0], ne[1], ne[2], f, c->stream));
@@ -2924,10 +3063,11 @@ static pft_status sis_step(pft_ctx* c, const UpdArgs& u)
     return PFT_OK;
 }
 
-pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, double* phi_a, double* phi_b,
-                       double* Q, double* H)
+// The field step of pft_cl_step; sb: the semi-implicit step's work memory, or
+// NULL for the context's own buffers.
+static pft_status cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, double* phi_a, double* phi_b,
+                          double* Q, double* H, const SisBufs* sb)
 {
-    if (!c) return PFT_E_INVALID;
     if (!st) return c->fail(PFT_E_INVALID, "step parameters are NULL");
     if (!(st->dt >= 0) || !(st->lambda_plus >= 0) || !(st->lambda_minus >= 0))
         return c->fail(PFT_E_INVALID, "dt and mobilities must be non-negative");
@@ -2967,11 +3107,18 @@ pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, d
         a.b_over_c = c->p.B / c->p.C;
         a.wm = nullptr;
     }
-    if (st->update == 1) return sis_step(c, a);
+    if (st->update == 1) return sis_step(c, a, sb);
     ProfScope ps(c, PFT_K_REDUCE, 6.0 * sizeof(double2) * (double)c->M);
     hipLaunchKernelGGL(k_update, dim3(grid_for((c->M + 3) / 4, 256)), dim3(256), 0, c->stream, a);
     PFT_HIP(c, hipGetLastError());
     return PFT_OK;
+}
+
+pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, double* phi_a, double* phi_b,
+                       double* Q, double* H)
+{
+    if (!c) return PFT_E_INVALID;
+    return cl_step(c, wp, wm, st, phi_a, phi_b, Q, H, nullptr);
 }
 
 pft_status pft_node_q(pft_ctx* c, double* qnode)

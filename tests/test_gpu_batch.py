@@ -208,32 +208,38 @@ def test_batch_walls_match_single_and_oracle(orc, prec):
         ctx.close()
 
 
-def test_batch_semi_implicit_between_reflecting_walls():
+@pytest.mark.parametrize("model", [B.PFT_DIBLOCK, B.PFT_EDWARDS])
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_batch_semi_implicit_between_reflecting_walls(prec, model):
     """Batched semi-implicit steps with reflecting walls (the filter on each
     replica's even image, one launch per pass over a group) equal the
-    single-context steps, periodic replicas of the same grid included."""
+    single-context steps, periodic replicas of the same grid included; both
+    precisions, diblock and Edwards replicas."""
     W = inputs.Workload
     reps = [W("a", (16, 24, 20), (2.0, 3.0, 2.5), 30, 0.4, 15.0, C=20.0, seed=21),
             W("b", (24, 24, 24), (3.0, 3.0, 3.0), 36, 0.45, 16.0, C=20.0, seed=22),
             W("c", (24, 24, 24), (3.0, 3.0, 3.0), 28, 0.35, 14.0, C=20.0, seed=23),
             W("d", (16, 24, 20), (2.5, 2.0, 3.0), 33, 0.5, 18.0, C=20.0, seed=24)]
     bcs = [(1, 0, 1), (0, 0, 1), (0, 0, 0), (1, 0, 1)]
-    params = [B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, B.PFT_C128, B.PFT_RQM4, B.PFT_DIBLOCK, 0.0,
+    ed = model == B.PFT_EDWARDS
+    params = [B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, B.PFT_RQM4, model, 1.3 if ed else 0.0,
                        B.PFT_STORE_BOTH, bc) for w, bc in zip(reps, bcs)]
     fields = [inputs.fields(w) for w in reps]
     bat = B.Batch(params)
     wp = [dev(f[0]) for f in fields]
-    wm = [dev(f[1]) for f in fields]
+    wm = None if ed else [dev(f[1]) for f in fields]
     bat.pft_batch_cl_steps(wp, wm, B.pft_step(0.2, 1.0, 0.5, 17, 60, 0, 1, 1), 2, None)
     bat.pft_batch_sync()
     for r, w in enumerate(reps):
         print("replica", r, w.n, bcs[r], flush=True)
         ctx = B.Context(params[r])
-        a, b = dev(fields[r][0]), dev(fields[r][1])
+        a = dev(fields[r][0])
+        b = None if ed else dev(fields[r][1])
         for stepno in range(2):
             ctx.pft_cl_step(a, b, B.pft_step(0.2, 1.0, 0.5, 17, 60 + r, stepno, 1, 1))
         assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
-        assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        if not ed:
+            assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
         ctx.close()
 
 
@@ -281,4 +287,53 @@ def test_batch_plain_split_matches_single(model, prec):
         assert np.abs(host(wp[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
         if not ed:
             assert np.abs(host(wm[r]) - host(b)).max() <= 1e-12 * np.abs(host(b)).max()
+        ctx.close()
+
+
+def test_batch_unsynced_calls_with_changing_pointers():
+    """Evaluations into new output buffers and re-captured field steps issued
+    back to back without a sync: each call's job tables are rewritten only
+    after the batch's queued work has drained, so every call lands in its own
+    buffers with the values of single contexts."""
+    reps, params, fields = replica_set(6, 81, B.PFT_C64)
+    n = len(reps)
+    bat = B.Batch(params)
+    wp = [dev(f[0]) for f in fields]
+    wm = [dev(f[1]) for f in fields]
+
+    def outputs():
+        pa = [torch.full(w.n, np.nan, dtype=torch.complex128, device=DEV) for w in reps]
+        pb = [torch.full(w.n, np.nan, dtype=torch.complex128, device=DEV) for w in reps]
+        return pa, pb, torch.zeros(n, dtype=torch.complex128, device=DEV), torch.zeros(n, dtype=torch.complex128, device=DEV)
+
+    o1, o2, o3 = outputs(), outputs(), outputs()
+    bat.pft_batch_evaluate(wp, wm, *o1)
+    bat.pft_batch_evaluate(wp, wm, *o2)              # new pointers, no sync
+    wp2 = [t.clone() for t in wp]
+    wm2 = [t.clone() for t in wm]
+    log = torch.zeros((2, n, 2), dtype=torch.complex128, device=DEV)
+    bat.pft_batch_cl_steps(wp2, wm2, B.pft_step(0.01, 1.0, 1.0, 9, 0, 0, 1), 2, log)   # capture
+    bat.pft_batch_evaluate(wp2, wm2, *o3)            # the stepped fields, new pointers
+    wp3 = [t.clone() for t in wp]
+    wm3 = [t.clone() for t in wm]
+    bat.pft_batch_cl_steps(wp3, wm3, B.pft_step(0.01, 1.0, 1.0, 9, 0, 0, 1), 1, None)  # re-capture
+    bat.pft_batch_sync()
+    for r, w in enumerate(reps):
+        ctx = B.Context(params[r])
+        ref = ctx.evaluate(wp[r], wm[r])
+        for o in (o1, o2):
+            assert np.abs(host(o[0][r]) - host(ref["phiA"])).max() <= 1e-13
+            assert np.abs(host(o[1][r]) - host(ref["phiB"])).max() <= 1e-13
+            assert abs(host(o[2])[r] - host(ref["Q"])[0]) <= 1e-13 * abs(host(ref["Q"])[0])
+        a, b = wp[r].clone(), wm[r].clone()
+        Qt = torch.empty(1, dtype=torch.complex128, device=DEV)
+        for stepno in range(2):
+            ctx.pft_cl_step(a, b, B.pft_step(0.01, 1.0, 1.0, 9, r, stepno, 1), None, None, Qt)
+            assert abs(host(log)[stepno, r, 0] - host(Qt)[0]) <= 1e-12 * abs(host(Qt)[0])
+            if stepno == 0:
+                assert np.abs(host(wp3[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        assert np.abs(host(wp2[r]) - host(a)).max() <= 1e-12 * np.abs(host(a)).max()
+        ref2 = ctx.evaluate(a, b)
+        assert np.abs(host(o3[0][r]) - host(ref2["phiA"])).max() <= 1e-13
+        assert abs(host(o3[2])[r] - host(ref2["Q"])[0]) <= 1e-13 * abs(host(ref2["Q"])[0])
         ctx.close()
