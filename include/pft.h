@@ -227,6 +227,18 @@ pft_status pft_densities(pft_ctx* ctx, double* phi_a, double* phi_b, double* Q);
 pft_status pft_evaluate_graph(pft_ctx* ctx, const double* w_plus, const double* w_minus, double* phi_a, double* phi_b,
                               double* Q, int32_t nreps);
 
+/* Change the box edges (lengths in R_g, each finite and > 0) of an existing
+ * context, keeping its grid, contour and buffers: the diffusion factors of
+ * Eq. (5) (k = 2 pi m / L, or pi m / L along a walled axis), the spectral
+ * second derivatives of the box derivative and, once built, the |k|^2 tables
+ * of the semi-implicit step are recomputed, and V, dV follow the new edges.
+ * This is the move a variable-cell calculation makes along dH/dL (the box
+ * derivative that pft_adjoint returns).  Blocks until the context's queued work
+ * has finished (that work reads the tables rewritten here); a pft_propagate
+ * is needed before pft_densities / pft_hamiltonian see the new box.
+ * Errors: PFT_E_INVALID, PFT_E_DEVICE. */
+pft_status pft_set_box(pft_ctx* ctx, double lx, double ly, double lz);
+
 /* Hamiltonian of Eq. (3) on the grid, H = C dV sum_x [w_-^2/chiN - i w_+]
  * - C V Log Q (principal branch), with Q from the last pft_propagate (which
  * must have used these fields).  H, h_intensive (= H / (C V)): 2 doubles out

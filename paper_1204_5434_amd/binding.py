@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 
 import torch  # loaded first so the library binds to torch's HIP runtime
 
@@ -35,7 +35,7 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_profile_end", "pft_copy_probe", "pft_adjoint", "pft_batch_create", "pft_batch_destroy",
            "pft_batch_last_error", "pft_batch_evaluate", "pft_batch_cl_steps", "pft_batch_sync",
            "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant", "pft_set_concurrent_sweeps",
-           "pft_set_fused_planes", "pft_fused_planes", "pft_evaluate_graph")
+           "pft_set_fused_planes", "pft_fused_planes", "pft_evaluate_graph", "pft_set_box")
 
 # Kernel variants per axis length (variant 0 always exists), at most MAX_VARIANTS.
 MAX_VARIANTS = 4
@@ -94,6 +94,7 @@ def load() -> ctypes.CDLL:
             "pft_densities": (i32, [vp, vp, vp, vp]),
             "pft_evaluate_graph": (i32, [vp, vp, vp, vp, vp, vp, i32]),
             "pft_hamiltonian": (i32, [vp, vp, vp, vp, vp]),
+            "pft_set_box": (i32, [vp, f64, f64, f64]),
             "pft_cl_step": (i32, [vp, vp, vp, P(pft_step), vp, vp, vp, vp]),
             "pft_node_q": (i32, [vp, vp]),
             "pft_get_slice": (i32, [vp, i32, i32, vp]),
@@ -238,6 +239,10 @@ class Context:
         self._check(load().pft_evaluate_graph(self._h, _field(w_plus, self.shape, "w_plus"), self._wm(w_minus),
                                               _field(phi_a, self.shape, "phi_a"),
                                               _field(phi_b, self.shape, "phi_b"), _opt(Q, (1,), "Q"), int(nreps)))
+
+    def pft_set_box(self, lx: float, ly: float, lz: float):
+        self._check(load().pft_set_box(self._h, float(lx), float(ly), float(lz)))
+        self.params = replace(self.params, lx=float(lx), ly=float(ly), lz=float(lz))
 
     def pft_hamiltonian(self, w_plus, w_minus, H, h_intensive=None):
         self._check(load().pft_hamiltonian(self._h, _field(w_plus, self.shape, "w_plus"),

@@ -193,3 +193,52 @@ def test_autograd_function_gradcheck():
     assert torch.autograd.gradcheck(lambda x, y: hamiltonian(ctx, x, y), (a.detach().requires_grad_(True),
                                     b.detach().requires_grad_(True)), eps=1e-6, atol=1e-7, rtol=1e-5,
                                     fast_mode=True)
+
+
+def test_set_box_equals_new_context(orc):
+    """pft_set_box moves a context to new edges: the evaluation and the
+    adjoint equal those of a context created with those edges, and the oracle."""
+    n, ns = (12, 8, 16), 14
+    wp, wm = fields(n, 26)
+    p0 = B.Params(*n, 3.0, 2.0, 4.0, ns, 0.45, 15.0, 2.0, B.PFT_C128, B.PFT_RQM4)
+    L1 = (3.3, 1.9, 4.4)
+    ctx = B.Context(p0)
+    ctx.evaluate(dev(wp), dev(wm))
+    ctx.pft_set_box(*L1)
+    out = ctx.evaluate(dev(wp), dev(wm))
+    ref_ctx = B.Context(B.Params(*n, *L1, ns, 0.45, 15.0, 2.0, B.PFT_C128, B.PFT_RQM4))
+    ref = ref_ctx.evaluate(dev(wp), dev(wm))
+    assert np.abs(host(out["phiA"]) - host(ref["phiA"])).max() == 0
+    assert host(out["H"])[0] == host(ref["H"])[0]
+    a1 = gpu_adjoint(ctx, dev(wp), dev(wm))
+    a2 = gpu_adjoint(ref_ctx, dev(wp), dev(wm))
+    assert np.array_equal(a1[2], a2[2]) and np.array_equal(a1[0], a2[0])
+    o = orc.evaluate(orc.Params(*n, *L1, ns, 0.45, 15.0, 2.0, 0, False), wp, wm)
+    assert abs(host(out["H"])[0] - o["H"]) <= 1e-11 * (abs(o["H"]) + 2.0 * np.prod(L1))
+    with pytest.raises(B.PftError):
+        ctx.pft_set_box(0.0, 1.0, 1.0)
+    ctx.close()
+    ref_ctx.close()
+
+
+def test_autograd_box_edges_gradcheck():
+    """The box edges as a differentiable input: dRe H/dL from backward equals
+    the real part of the box derivative, and gradcheck passes on L alone and
+    on (w+, w-, L) together."""
+    n = (8, 12, 8)
+    wp, wm = fields(n, 27)
+    ctx = B.Context(B.Params(*n, 2.0, 3.0, 2.0, 12, 0.4, 15.0, 1.5, B.PFT_C128, B.PFT_RQM4))
+    L = torch.tensor([2.1, 2.9, 2.2], dtype=torch.float64, requires_grad=True)
+    H = hamiltonian(ctx, dev(wp), dev(wm), L)
+    H.real.backward()
+    ref = gpu_adjoint(ctx, dev(wp), dev(wm))
+    assert (ctx.params.lx, ctx.params.ly, ctx.params.lz) == (2.1, 2.9, 2.2)
+    assert np.allclose(L.grad.numpy(), ref[2].real, rtol=1e-14, atol=0)
+    a, b = dev(wp), dev(wm)
+    assert torch.autograd.gradcheck(lambda x: hamiltonian(ctx, a, b, x), (L.detach().requires_grad_(True),),
+                                    eps=1e-6, atol=1e-7, rtol=1e-5)
+    assert torch.autograd.gradcheck(lambda x, y, z: hamiltonian(ctx, x, y, z),
+                                    (a.clone().requires_grad_(True), b.clone().requires_grad_(True),
+                                     L.detach().requires_grad_(True)),
+                                    eps=1e-6, atol=1e-7, rtol=1e-5, fast_mode=True)
+    ctx.close()
