@@ -95,6 +95,36 @@ def test_cl64_thousand_steps(orc, prec, tol):
     assert ctx.pft_status_flags() == 0
 
 
+def test_cl64_single_and_double_precision_mean_H():
+    """The 64^3 Langevin run (1000 steps, same seed and noise stream) with
+    complex64 and with complex128 propagators: the block-averaged Re H of the
+    two runs agree within their statistical error (the single- against
+    double-precision comparison of Sec. V).  Steps 0-199 are discarded; the
+    rest is cut into 8 blocks of 100 steps."""
+    w = inputs.CL64
+    wp, wm = inputs.fields(w)
+    series = {}
+    for prec in (B.PFT_C128, B.PFT_C64):
+        ctx = B.Context(B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, B.PFT_RQM4))
+        gwp, gwm = dev(wp), dev(wm)
+        hlog = torch.empty(w.steps, dtype=torch.complex128, device=DEV)
+        for step in range(w.steps):
+            ctx.pft_cl_step(gwp, gwm, B.pft_step(w.dt, 1.0, 1.0, w.seed, 0, step, 1), None, None, None,
+                            hlog[step:step + 1])
+        series[prec] = host(hlog)
+        assert np.isfinite(series[prec]).all()
+        ctx.close()
+    stats = {}
+    for prec, h in series.items():
+        blocks = h.real[200:].reshape(8, 100).mean(axis=1)
+        stats[prec] = (blocks.mean(), blocks.std(ddof=1) / np.sqrt(len(blocks)))
+    (m64, s64), (m32, s32) = stats[B.PFT_C128], stats[B.PFT_C64]
+    drift = np.abs(series[B.PFT_C64] - series[B.PFT_C128]).max() / np.abs(series[B.PFT_C128]).max()
+    say(f"cl64 <Re H>: FP64 {m64:.6f} +- {s64:.6f}, FP32 {m32:.6f} +- {s32:.6f}; "
+        f"largest per-step |H32 - H64| / max|H64| = {drift:.3e}")
+    assert abs(m64 - m32) <= 3.0 * np.hypot(s64, s32)
+
+
 def test_cl256_large_single_gpu(orc):
     w = inputs.CL256
     say("cl256: complex64 stores of", 2 * 201 * w.M * 8 / 1e9, "GB")
