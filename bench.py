@@ -137,7 +137,14 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
     flags = ctx.pft_status_flags()
     if flags:
         raise RuntimeError(f"device status flags {flags:#x}")
+    # the results of one evaluation (outside every timed region), for the
+    # error report against the oracle
+    Hd = torch.empty(1, dtype=torch.complex128, device="cuda")
+    evaluate()
+    ctx.pft_hamiltonian(wp, wm, Hd)
+    torch.cuda.synchronize()
     Qv = complex(Q.cpu()[0])
+    results = {"phiA": phiA.cpu().numpy(), "phiB": phiB.cpu().numpy(), "Q": Qv, "H": complex(Hd.cpu()[0])}
     ctx.close()
     site_steps = 2.0 * w.M * w.ns
     rate = site_steps / (ms * 1e-3)
@@ -157,7 +164,20 @@ def run_precision(binding, w, wp, wm, precision, steps, warmup, scheme):
                  for k, v in prof.items() if v[1] > 0}
     bytes_eval = sum(v[2] for v in prof.values()) / steps
     roof["aggregate_GB_s"] = round(bytes_eval / (ms * 1e-3) / 1e9, 1)
-    out = {"value": rate, "ms_per_step": ms, "ms_per_evaluation_spread": spread, "ms_per_step_graph": ms_graph,
+    # frac above is the dominant kernel's own (its bytes per launch over its
+    # duration, launches timed one at a time on one stream); beside it, the
+    # whole evaluation against the method's minimum traffic: per site-step
+    # the forward step reads q_j and the block's two field tables and writes
+    # q_{j+1} (4c), the conjugate step also reads the stored q slice and
+    # updates an FP64 complex density accumulator (5c + 32): (9c + 32) / 2
+    c_bytes = 16 if precision == "f64" else 8
+    floor = (9 * c_bytes + 32) / 2
+    roof["frac_of"] = "dominant kernel per launch (one-stream repeat, launches isolated)"
+    roof["bytes_per_site_step"] = round(bytes_eval / site_steps, 1)
+    roof["floor_bytes_per_site_step"] = floor
+    roof["floor_GB_s"] = round(floor * rate / 1e9, 1)
+    roof["floor_frac"] = round(floor * rate / 1e9 / HBM_PEAK_GBS, 4)
+    out = {"value": rate, "results": results, "ms_per_step": ms, "ms_per_evaluation_spread": spread, "ms_per_step_graph": ms_graph,
            "ms_per_step_one_stream": ms_single, "roofline": roof,
            "kernels": breakdown, "Q": [Qv.real, Qv.imag],
            "schedule": {0: "axis", 1: "fused", 2: "fused-conjugate-sweep"}[fused]}
@@ -437,16 +457,165 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, wp, wm, seconds: float, threads: int = 0):
-    """The FP64 oracle on a bounded sample: forward-sweep Richardson steps of
-    the same 128^3 workload on `threads` host threads (0: all, at most 16),
-    until `seconds` elapse."""
+def large_grid_run(binding, inputs, steps: int):
+    """The large single-GPU workload (256^3, Ns = 200, f = 0.35, chi N = 22,
+    L = 16, C = 100): evaluations and Langevin steps (dt = 0.005) in both
+    working precisions, per-pass bandwidth from a profiled evaluation on one
+    stream, and one checkpointed reverse-mode pass in complex64.  One 256^3
+    array is 268 MB in complex128 and 134 MB in complex64, so the passes'
+    arrays no longer fit the 256 MB Infinity Cache together."""
+    import torch
+    w = inputs.CL256
+    wp, wm = (torch.from_numpy(a).to("cuda") for a in inputs.fields(w))
+    out = {"workload": w.name, "grid": list(w.n), "box": list(w.L), "ns": w.ns, "f": w.f, "chiN": w.chiN,
+           "C": w.C, "site_steps_per_evaluation": 2 * w.M * w.ns}
+    for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4))
+        dev_gb = (free0 - torch.cuda.mem_get_info()[0]) / 1e9
+        pa = torch.empty(w.n, dtype=torch.complex128, device="cuda")
+        pb = torch.empty_like(pa)
+
+        def evaluate():
+            ctx.pft_propagate(wp, wm)
+            ctx.pft_densities(pa, pb)
+
+        evaluate()
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(steps):
+            evaluate()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        a, b = wp.clone(), wm.clone()
+        ctx.pft_cl_step(a, b, binding.pft_step(w.dt, 1.0, 1.0, w.seed, 0, 0, 1))
+        torch.cuda.synchronize()
+        t0.record()
+        for k in range(steps):
+            ctx.pft_cl_step(a, b, binding.pft_step(w.dt, 1.0, 1.0, w.seed, 0, 1 + k, 1))
+        t1.record()
+        torch.cuda.synchronize()
+        ms_cl = t0.elapsed_time(t1) / steps
+        del a, b
+        ctx.pft_set_concurrent_sweeps(False)
+        ctx.pft_profile_begin()
+        evaluate()
+        prof = ctx.pft_profile_end()
+        ctx.pft_set_concurrent_sweeps(True)
+        res = {"ms_per_evaluation": ms, "value": 2 * w.M * w.ns / (ms * 1e-3), "ms_per_cl_step": ms_cl,
+               "device_GB": round(dev_gb, 1),
+               "kernels": {k: {"ms_per_evaluation": round(v[0], 3), "launches": int(v[1]),
+                               "GB_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
+                           for k, v in prof.items() if v[1] > 0}}
+        if prec == binding.PFT_C64:
+            gp = torch.empty(w.n, dtype=torch.complex128, device="cuda")
+            gm = torch.empty_like(gp)
+            dL = torch.empty(3, dtype=torch.complex128, device="cuda")
+            torch.cuda.synchronize()
+            t0.record()
+            ctx.pft_adjoint(wp, wm, gp, gm, dL, None, 0)
+            t1.record()
+            torch.cuda.synchronize()
+            res["adjoint_ms"] = t0.elapsed_time(t1)
+            del gp, gm, dL
+        if ctx.pft_status_flags():
+            raise RuntimeError("device status flags set in the 256^3 run")
+        ctx.close()
+        del pa, pb
+        out[name] = res
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _errors(gpu, ref, w):
+    """Per-result error of one GPU evaluation against the oracle's: phi
+    relative to max|phi|, Q relative, H on |H| + C V and relative to |H|."""
     import numpy as np
+    scale = max(np.abs(ref["phiA"]).max(), np.abs(ref["phiB"]).max())
+    dH = abs(gpu["H"] - ref["H"])
+    return {"phiA": float(np.abs(gpu["phiA"] - ref["phiA"]).max() / scale),
+            "phiB": float(np.abs(gpu["phiB"] - ref["phiB"]).max() / scale),
+            "Q": abs(gpu["Q"] - ref["Q"]) / abs(ref["Q"]),
+            "H": dH / (abs(ref["H"]) + w.C * w.L[0] * w.L[1] * w.L[2]),
+            "H_relative_to_H": dH / abs(ref["H"])}
+
+
+def cpu_baseline(binding, inputs, w, wp, wm, gpu_results, seconds_one_thread: float):
+    """The FP64 oracle as it stands, on the host cores.
+
+    On all visible cores (at most 16): one full evaluation of the workload
+    (both sweeps, densities, Q, H), whose results also give the per-result
+    error of the GPU evaluations in both precisions; the 16^3 relaxation in
+    full (100 iterations); one 64^3 Langevin step.  On one thread: a bounded
+    sample of forward-sweep steps of the workload.  Also the reverse-mode
+    error (dH/dw, dH/dL) of both precisions on the gradient state at 48^3,
+    Ns = 64 (a reduced copy of the 96^3 state the oracle would take minutes
+    on)."""
+    import numpy as np
+    import torch
     from oracle import oracle
-    if threads <= 0:
-        threads = min(len(os.sched_getaffinity(0)), 16)
+    threads = min(len(os.sched_getaffinity(0)), 16)
     oracle.set_threads(threads)
     p = oracle.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, 0)
+    t = time.perf_counter()
+    ref = oracle.evaluate(p, wp, wm)
+    el = time.perf_counter() - t
+    base = {"value": 2.0 * w.M * w.ns / el, "unit": "grid-pts×steps/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(), "host_cores_visible": len(os.sched_getaffinity(0)),
+            "sample": f"one full evaluation of the {w.name} workload ({2 * ref['K']} Richardson steps over "
+                      f"both sweeps, densities, Q and H): {el:.1f} s"}
+    errors = {name: _errors(g, ref, w) for name, g in gpu_results.items()}
+    del ref
+    legs = {}
+    s16 = inputs.SCFT16
+    p16 = oracle.Params(*s16.n, *s16.L, s16.ns, s16.f, s16.chiN, s16.C, 0)
+    a, b = inputs.fields(s16)
+    t = time.perf_counter()
+    for _ in range(s16.steps):
+        r = oracle.evaluate(p16, a, b)
+        a, b = oracle.em_update(p16, a, b, r["phiA"], r["phiB"], s16.dt)
+    legs["scft16_full_100_iterations_s"] = round(time.perf_counter() - t, 3)
+    c64 = inputs.CL64
+    p64 = oracle.Params(*c64.n, *c64.L, c64.ns, c64.f, c64.chiN, c64.C, 0)
+    a, b = inputs.fields(c64)
+    t = time.perf_counter()
+    r = oracle.evaluate(p64, a, b)
+    oracle.em_update(p64, a, b, r["phiA"], r["phiB"], c64.dt, noise=True, seed=c64.seed, replica=0, step_=0)
+    legs["cl64_one_step_s"] = round(time.perf_counter() - t, 3)
+    legs["cores"] = threads
+    # reverse mode at 48^3, Ns = 64: oracle against both GPU precisions
+    g = inputs.GRAD96.scaled((48, 48, 48), ns=64)
+    ga, gb = inputs.fields(g)
+    rp, rm, rL = oracle.adjoint(oracle.Params(*g.n, *g.L, g.ns, g.f, g.chiN, g.C, 0), ga, gb)
+    adj = {"workload": f"{g.name} at 48^3, Ns = 64 (f = {g.f}, junction inside a step)"}
+    V = g.L[0] * g.L[1] * g.L[2]
+    for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+        ctx = binding.Context(binding.Params(*g.n, *g.L, g.ns, g.f, g.chiN, g.C, prec, binding.PFT_RQM4))
+        gp = torch.empty(g.n, dtype=torch.complex128, device="cuda")
+        gm = torch.empty_like(gp)
+        dL = torch.empty(3, dtype=torch.complex128, device="cuda")
+        ctx.pft_adjoint(torch.from_numpy(ga).to("cuda"), torch.from_numpy(gb).to("cuda"), gp, gm, dL, None, 8)
+        gp, gm, dL = gp.cpu().numpy(), gm.cpu().numpy(), dL.cpu().numpy()
+        ctx.close()
+        adj[name] = {"dH_dwplus": float(np.abs(gp - rp).max() / np.abs(rp).max()),
+                     "dH_dwminus": float(np.abs(gm - rm).max() / np.abs(rm).max()),
+                     "dH_dL": max(abs(dL[k] - rL[k]) / (abs(rL[k]) + g.C * V / g.L[k]) for k in range(3)),
+                     "dH_dL_relative_to_dL": max(abs(dL[k] - rL[k]) / abs(rL[k]) for k in range(3))}
+    errors["adjoint"] = adj
+    # one thread, bounded sample of forward-sweep steps
+    oracle.set_threads(1)
     wA, _ = oracle.block_fields(p, wp, wm)
     h, _, _ = oracle.contour(w.ns, w.f)
     q = np.ones(w.n, complex)
@@ -456,12 +625,12 @@ def cpu_baseline(w, wp, wm, seconds: float, threads: int = 0):
         q = oracle.step(p, h[n % len(h)], wA, q)
         n += 1
         el = time.perf_counter() - t
-        if el >= seconds:
+        if el >= seconds_one_thread:
             break
-    return {"value": n * w.M / el, "unit": "grid-pts×steps/s", "cores": oracle.get_threads(),
-            "kind": "oracle", "cpu": cpu_model(), "host_cores_visible": len(os.sched_getaffinity(0)),
-            "sample": f"{n} forward-sweep Richardson steps of the {w.n[0]}^3 workload ({el:.1f} s); "
-                      "the density reduction (~1% of the GPU time) is not in the sample"}
+    one = {"value": n * w.M / el, "unit": "grid-pts×steps/s", "cores": oracle.get_threads(), "kind": "oracle",
+           "cpu": cpu_model(), "sample": f"{n} forward-sweep Richardson steps of the {w.n[0]}^3 workload "
+                                         f"({el:.1f} s); the density reduction is not in the sample"}
+    return base, one, legs, errors
 
 
 def main():
@@ -471,7 +640,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lam128")
     ap.add_argument("--scheme", default="rqm4", choices=["rqm4", "split2"])
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=5.0,
+                    help="length of the one-thread oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="both", choices=["both", "f64", "f32"])
     ap.add_argument("--no-autotune", action="store_true",
@@ -483,6 +653,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-edwards", action="store_true",
                     help="skip the side measurements (other scheme, storage modes, field update, walls, adjoint, Edwards)")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256^3 measurement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the library's plain copy kernel on this many MiB (counter scale)")
     args = ap.parse_args()
@@ -573,19 +744,24 @@ def main():
         log("[bench] Edwards homopolymer model, 128^3, Ns = 100")
         edwards = edwards_run(binding, inputs, args.steps, args.warmup)
         log(f"[bench] edwards: {edwards}")
+    large = None
+    if not args.no_edwards and not args.no_large:
+        log("[bench] large grid: 256^3, Ns = 200")
+        large = large_grid_run(binding, inputs, max(2, args.steps // 4))
+        log(f"[bench] large grid: {large}")
     batched = None
     if args.batch_replicas > 0:
         log(f"[bench] batched replicas: {args.batch_replicas}, {args.batch_steps} field steps")
         batched = batched_gain(binding, inputs, args.batch_replicas, args.batch_steps)
         log(f"[bench] batched: {batched}")
-    cpu = None
-    cpu1 = None
+    cpu = cpu1 = legs = errors = None
     if not args.no_cpu_baseline:
-        log(f"[bench] cpu baseline: oracle for ~{args.cpu_seconds} s")
-        cpu = cpu_baseline(w, wp_np, wm_np, args.cpu_seconds)
-        log(f"[bench] cpu baseline: {cpu}")
-        cpu1 = cpu_baseline(w, wp_np, wm_np, max(3.0, args.cpu_seconds / 3), threads=1)
-        log(f"[bench] cpu baseline, one thread: {cpu1}")
+        log("[bench] cpu baseline: one full oracle evaluation, the 16^3 relaxation, one 64^3 step, "
+            "the 48^3 reverse mode, a one-thread sample")
+        gpu_results = {k: v["results"] for k, v in res.items()}
+        cpu, cpu1, legs, errors = cpu_baseline(binding, inputs, w, wp_np, wm_np, gpu_results, args.cpu_seconds)
+        log(f"[bench] cpu baseline: {cpu} {cpu1} {legs}")
+        log(f"[bench] errors against the oracle: {errors}")
     main_ = res["f64"] if "f64" in res else res["f32"]
     line = {
         "metric": METRIC,
@@ -608,6 +784,7 @@ def main():
         "roofline": main_["roofline"],
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,
+        "cpu_legs": legs,
         "kernels": main_["kernels"],
         "schedule": main_["schedule"],
     }
@@ -629,6 +806,12 @@ def main():
         line["other_scheme"] = other
     if adjoint is not None:
         line["adjoint"] = adjoint
+    if large is not None:
+        line["large_grid"] = large
+    if errors is not None:
+        line["error"] = {"vs": "FP64 oracle; one full evaluation of the workload (phi relative to max|phi|, "
+                               "Q relative, H on |H| + C V); reverse mode on the reduced gradient state",
+                         "f64": errors.get("f64"), "adjoint": errors.get("adjoint")}
     if "f64" in res and "f32" in res:
         line["fp32"] = {"value": res["f32"]["value"], "ms_per_step": res["f32"]["ms_per_step"],
                         "ms_per_step_one_stream": res["f32"]["ms_per_step_one_stream"],
@@ -638,6 +821,8 @@ def main():
                         "ms_per_evaluation_spread": res["f32"]["ms_per_evaluation_spread"]}
         if "ms_per_step_by_schedule" in res["f32"]:
             line["fp32"]["ms_per_step_by_schedule"] = res["f32"]["ms_per_step_by_schedule"]
+        if errors is not None:
+            line["fp32"]["error"] = dict(errors["f32"], adjoint=errors["adjoint"]["f32"])
     print(json.dumps(line))
 
 
