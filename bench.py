@@ -457,6 +457,35 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def langevin_run(binding, inputs, steps: int):
+    """The 64^3 complex-Langevin workload (Ns = 100, f = 0.4, chi N = 20,
+    C = 50, dt = 0.01, real Gaussian noise): Langevin steps (evaluation, H and
+    the update) per second with complex128 and with complex64 propagators."""
+    import torch
+    w = inputs.CL64
+    wp0, wm0 = (torch.from_numpy(a).to("cuda") for a in inputs.fields(w))
+    out = {"workload": w.name, "grid": list(w.n), "ns": w.ns, "site_steps_per_cl_step": 2 * w.M * w.ns}
+    for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
+        ctx = binding.Context(binding.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, binding.PFT_RQM4))
+        a, b = wp0.clone(), wm0.clone()
+        ctx.pft_cl_step(a, b, binding.pft_step(w.dt, 1.0, 1.0, w.seed, 0, 0, 1))
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for k in range(steps):
+            ctx.pft_cl_step(a, b, binding.pft_step(w.dt, 1.0, 1.0, w.seed, 0, 1 + k, 1))
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / steps
+        if ctx.pft_status_flags():
+            raise RuntimeError("device status flags set in the 64^3 Langevin run")
+        out[name] = {"ms_per_cl_step": ms, "cl_steps_per_s": 1e3 / ms,
+                     "value": 2 * w.M * w.ns / (ms * 1e-3),
+                     "schedule": {0: "axis", 1: "fused", 2: "fused"}[ctx.pft_fused_planes()]}
+        ctx.close()
+    return out
+
+
 def large_grid_run(binding, inputs, steps: int):
     """The large single-GPU workload (256^3, Ns = 200, f = 0.35, chi N = 22,
     L = 16, C = 100): evaluations and Langevin steps (dt = 0.005) in both
@@ -744,6 +773,11 @@ def main():
         log("[bench] Edwards homopolymer model, 128^3, Ns = 100")
         edwards = edwards_run(binding, inputs, args.steps, args.warmup)
         log(f"[bench] edwards: {edwards}")
+    langevin = None
+    if not args.no_edwards:
+        log("[bench] Langevin steps at 64^3, Ns = 100")
+        langevin = langevin_run(binding, inputs, max(10, args.steps))
+        log(f"[bench] langevin: {langevin}")
     large = None
     if not args.no_edwards and not args.no_large:
         log("[bench] large grid: 256^3, Ns = 200")
@@ -806,6 +840,8 @@ def main():
         line["other_scheme"] = other
     if adjoint is not None:
         line["adjoint"] = adjoint
+    if langevin is not None:
+        line["langevin_64"] = langevin
     if large is not None:
         line["large_grid"] = large
     if errors is not None:
