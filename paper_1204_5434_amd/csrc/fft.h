@@ -344,16 +344,35 @@ __device__ __forceinline__ void dft(cx<T>* v)
 // lay(k1, n2) maps an element of the exchanged N1 x N2 matrix of this lane's
 // line to its LDS slot.  Every lane of the workgroup must call diffuse()
 // (it contains barriers); lanes without a line pass zeros.
-template <int N1, int N2, typename T, class Lay, class G>
+//
+// MEAN (diffusion factors, whose k = 0 entry is 1/N): in complex float the
+// k = 0 mode is divided by N in double and rounded once, instead of being
+// multiplied by 1/N rounded to float.  1/N is not a float for N with a factor
+// 3 or 5, and its rounding error would scale the mean of q by the same factor
+// in every pass of every contour step, an error that grows linearly with the
+// number of steps in Q.
+template <int N, typename T>
+__device__ __forceinline__ cx<T> mean_over_n(cx<T> x)
+{
+    constexpr double inv = 1.0 / N;
+    return {T(double(x.re) * inv), T(double(x.im) * inv)};
+}
+
+template <int N1, int N2, bool MEAN = false, typename T, class Lay, class G>
 __device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay, const G& g)
 {
     constexpr int N = N1 * N2;
+    constexpr bool kMean = MEAN && std::is_same<T, float>::value;
     if constexpr (N2 == 1) {
         dft<N1, false>(a);
         sfor<0, N1>([&](auto K) {
             constexpr int k = decltype(K)::value;
-            const T gk = g[k];
-            a[k] = gk * a[k];
+            if constexpr (kMean && k == 0) {
+                a[0] = mean_over_n<N>(a[0]);
+            } else {
+                const T gk = g[k];
+                a[k] = gk * a[k];
+            }
         });
         dft<N1, true>(a);
     } else {
@@ -375,7 +394,10 @@ __device__ __forceinline__ void diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict
             sfor<0, N2>([&](auto K2) {
                 constexpr int k2 = decltype(K2)::value;
                 const T gk = g[k1 + N1 * k2];
-                b[k2] = gk * b[k2];
+                if constexpr (kMean && i == 0 && k2 == 0)
+                    b[0] = (t == 0) ? mean_over_n<N>(b[0]) : gk * b[0];  // k1 = t: lane 0 holds k = 0
+                else
+                    b[k2] = gk * b[k2];
             });
             dft<N2, true>(b);
             sfor<0, N2>([&](auto M2) { sh[lay(k1, decltype(M2)::value)] = b[decltype(M2)::value]; });

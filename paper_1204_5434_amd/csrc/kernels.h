@@ -100,15 +100,31 @@ __device__ __forceinline__ T ext_sign(int n)
     return (EXT == 2 && n >= N / 2) ? T(-1) : T(1);
 }
 
-// The line diffusion of the periodic (EXT = 0) or walled line.
-template <int EXT, int N1, int N2, typename T, class Lay>
+// The line diffusion of the periodic (EXT = 0) or walled line; MEAN as in
+// diffuse() (tables of diffusion factors).
+template <int EXT, int N1, int N2, bool MEAN = false, typename T, class Lay>
 __device__ __forceinline__ void line_diffuse(cx<T> (&a)[N1], int t, cx<T>* __restrict__ sh, const Lay& lay,
                                              const T* __restrict__ g)
 {
     if constexpr (EXT == 0)
-        diffuse<N1, N2>(a, t, sh, lay, g);
+        diffuse<N1, N2, MEAN>(a, t, sh, lay, g);
     else
         pair_diffuse<N1, N2>(a, t, sh, lay, g);
+}
+
+// The Richardson combination (4 u - v) / 3 of Eq. (12).  In complex float it
+// is formed in double and rounded once: multiplying by 1/3 rounded to float
+// would scale every node by the same factor at every step.
+template <typename T>
+__device__ __forceinline__ cx<T> richardson(cx<T> u, cx<T> v)
+{
+    if constexpr (std::is_same<T, float>::value) {
+        constexpr double third = 1.0 / 3.0;
+        return {float((4.0 * double(u.re) - double(v.re)) * third), float((4.0 * double(u.im) - double(v.im)) * third)};
+    } else {
+        constexpr T third = T(1.0 / 3.0);
+        return third * (T(4) * u - v);
+    }
 }
 
 template <typename T, int N1, int N2, int W, int EXT = 0>
@@ -184,9 +200,8 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
     if (A.has_prev) {
         if (A.scheme == kSchemeRQM4) {
             load(A.U, q);
-            line_diffuse<EXT, N1, N2>(q, t, sh, lay, A.gh_p);
+            line_diffuse<EXT, N1, N2, true>(q, t, sh, lay, A.gh_p);
             if (A.hcap) store(A.hcap, q);
-            constexpr T third = T(1.0 / 3.0);
             if (A.Ep) {
                 load_e(A.Ep, e);
                 have_e = true;
@@ -195,7 +210,7 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
                     const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
-                    q[i] = third * (T(4) * u - at(A.V, i));
+                    q[i] = richardson(u, at(A.V, i));
                 });
             }
         } else {
@@ -234,10 +249,10 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
             sfor<0, N1>([&](auto I) { w[decltype(I)::value] = q[decltype(I)::value]; });
         }
         if (A.scheme == kSchemeRQM4) {
-            line_diffuse<EXT, N1, N2>(q, t, sh, lay, A.gh_n);
+            line_diffuse<EXT, N1, N2, true>(q, t, sh, lay, A.gh_n);
             store(A.U, q);
         }
-        line_diffuse<EXT, N1, N2>(w, t, sh, lay, A.gf_n);
+        line_diffuse<EXT, N1, N2, true>(w, t, sh, lay, A.gf_n);
         store(A.V, w);
     }
 }
@@ -343,7 +358,7 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
     };
     // one array: diffuse, [capture], [multiply by e2 = E4^2, diffuse again]
     auto run_on = [&](cx<T>* X, cx<T>(&a)[N1], const SOps<T>& op, const cx<T>(&e2)[N1], bool have_e2) {
-        line_diffuse<EXT, N1, N2>(a, t, sh, lay, op.g1);
+        line_diffuse<EXT, N1, N2, true>(a, t, sh, lay, op.g1);
         if (op.acap) stX(op.acap, a);
         if (AXIS == 0 && op.e) {  // field multiplies happen only in the x pass
             if (have_e2) {
@@ -355,7 +370,7 @@ __device__ __forceinline__ void spass_body(const SArgs<T>& A, unsigned bid, cx<T
                     a[i] = a[i] * (e * e);
                 });
             }
-            if (op.g2) line_diffuse<EXT, N1, N2>(a, t, sh, lay, op.g2);
+            if (op.g2) line_diffuse<EXT, N1, N2, true>(a, t, sh, lay, op.g2);
         }
         stX(X, a);
     };

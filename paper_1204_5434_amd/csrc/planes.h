@@ -159,11 +159,10 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
     if (A.has_prev) {
         if (A.scheme == kSchemeRQM4) {
             ldc(A.U, q);
-            diffuse<N1, N2>(q, ty, sh, lay_c, A.gyh_p);
+            diffuse<N1, N2, true>(q, ty, sh, lay_c, A.gyh_p);
             to_rows(q);
-            diffuse<N1, N2>(q, tz, sh, lay_r, A.gzh_p);
+            diffuse<N1, N2, true>(q, tz, sh, lay_r, A.gzh_p);
             if (A.hcap) str(A.hcap, q);
-            constexpr T third = T(1.0 / 3.0);
             const cx<T>* Vp = A.V + pbase;
             if (A.Ep) {
                 ldr(A.Ep, e);
@@ -173,7 +172,7 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
                 constexpr int i = decltype(I)::value;
                 const cx<T> v = act ? Vp[ro + i * N2] : cx<T>{T(0), T(0)};
                 const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
-                q[i] = third * (T(4) * u - v);
+                q[i] = richardson(u, v);
             });
         } else {
             ldr(A.V, q);
@@ -207,14 +206,14 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
             sfor<0, N1>([&](auto I) { w[decltype(I)::value] = q[decltype(I)::value]; });
         }
         if (A.scheme == kSchemeRQM4) {
-            diffuse<N1, N2>(q, tz, sh, lay_r, A.gzh_n);
+            diffuse<N1, N2, true>(q, tz, sh, lay_r, A.gzh_n);
             to_cols(q);
-            diffuse<N1, N2>(q, ty, sh, lay_c, A.gyh_n);
+            diffuse<N1, N2, true>(q, ty, sh, lay_c, A.gyh_n);
             stc(A.U, q);
         }
-        diffuse<N1, N2>(w, tz, sh, lay_r, A.gzf_n);
+        diffuse<N1, N2, true>(w, tz, sh, lay_r, A.gzf_n);
         to_cols(w);
-        diffuse<N1, N2>(w, ty, sh, lay_c, A.gyf_n);
+        diffuse<N1, N2, true>(w, ty, sh, lay_c, A.gyf_n);
         stc(A.V, w);
     }
 }
