@@ -42,6 +42,7 @@ class PftHamiltonian(torch.autograd.Function):
             dL = torch.empty(3, dtype=torch.complex128, device=w_plus.device) if need_L else None
             pft.pft_adjoint(w_plus.detach(), w_minus.detach(), gp, gm, dL, H, ckpt_every)
             fctx.save_for_backward(gp, gm, dL)
+            fctx.L_device = L.device if L is not None else None
         else:
             pft.pft_propagate(w_plus, w_minus)
             pft.pft_hamiltonian(w_plus, w_minus, H)
@@ -50,7 +51,7 @@ class PftHamiltonian(torch.autograd.Function):
     @staticmethod
     def backward(fctx, g):
         gp, gm, dL = fctx.saved_tensors
-        gL = None if dL is None else (g * dL.conj()).real.to(torch.float64)
+        gL = None if dL is None else (g * dL.conj()).real.to(device=fctx.L_device, dtype=torch.float64)
         return None, g * gp.conj(), g * gm.conj(), gL, None
 
 

@@ -2059,25 +2059,39 @@ template <typename T>
 pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
 {
     const int R = (int)g.reps.size();
-    std::vector<pft::ZArgs<T>> zd(g.fused ? 0 : (size_t)2 * (g.maxK + 1) * R);
-    std::vector<pft::PArgs<T>> pd(g.fused ? (size_t)2 * (g.maxK + 1) * R : 0);
-    std::vector<pft::SArgs<T>> sd((size_t)2 * g.maxK * g.npass * R);
+    const int D = g.ndir;
+    std::vector<pft::ZArgs<T>> zd(g.fused ? 0 : (size_t)D * (g.maxK + 1) * R);
+    std::vector<pft::PArgs<T>> pd(g.fused ? (size_t)D * (g.maxK + 1) * R : 0);
+    std::vector<pft::SArgs<T>> sd((size_t)D * g.maxK * g.npass * R);
     for (int dir = 0; dir < g.ndir; ++dir)
         for (int ri = 0; ri < R; ++ri) {
             pft_ctx* c = b->ctx[g.reps[ri]];
             const int K = c->K;
             auto stepj = [&](int i) { return dir ? K - 1 - i : i; };
             void* store = dir ? c->qds : c->qs;
+            // the two sweeps advance in the same launches, so each has its own work pair
+            cx<T>* wU = static_cast<cx<T>*>(dir ? c->U2 : c->U);
+            cx<T>* wV = static_cast<cx<T>*>(dir ? c->V2 : c->V);
             for (int p = 0; p <= g.maxK; ++p) {
                 const int i = p - 1;  // Z (or yz) at position p completes step i and starts step i + 1
-                const size_t at = ((size_t)dir * (g.maxK + 1) + p) * R + ri;
+                const size_t at = ((size_t)p * D + dir) * R + ri;
                 const int prev = i >= 0 ? stepj(i) : -1, next = i + 1 < K ? stepj(i + 1) : -1;
                 if (g.fused) {
-                    if (i >= K) pd[at].skip = 1;
-                    else pd[at] = pargs<T>(c, prev, next, nullptr, slice<T>(store, c, i + 1));
+                    if (i >= K) {
+                        pd[at].skip = 1;
+                    } else {
+                        pd[at] = pargs<T>(c, prev, next, nullptr, slice<T>(store, c, i + 1));
+                        pd[at].U = wU;
+                        pd[at].V = wV;
+                    }
                 } else {
-                    if (i >= K) zd[at].skip = 1;
-                    else zd[at] = zargs<T>(c, prev, next, nullptr, slice<T>(store, c, i + 1));
+                    if (i >= K) {
+                        zd[at].skip = 1;
+                    } else {
+                        zd[at] = zargs<T>(c, prev, next, nullptr, slice<T>(store, c, i + 1));
+                        zd[at].U = wU;
+                        zd[at].V = wV;
+                    }
                 }
             }
             for (int p = 0; p < g.maxK; ++p) {
@@ -2085,12 +2099,14 @@ pft_status batch_build_pass_tables(pft_batch* b, BatchGroup& g)
                 pft::SArgs<T> sa[3];
                 if (p < K) body_passes<T>(c, stepj(p), ax, sa);
                 for (int k = 0; k < g.npass; ++k) {
-                    pft::SArgs<T>& d = sd[(((size_t)dir * g.maxK + p) * g.npass + k) * R + ri];
+                    pft::SArgs<T>& d = sd[(((size_t)p * g.npass + k) * D + dir) * R + ri];
                     if (p >= K) {
                         d.skip = 1;
                         continue;
                     }
                     d = g.fused ? sa[1] : sa[k];  // fused: the x pass alone
+                    d.U = wU;
+                    d.V = wV;
                     const int axk = g.sp_axis[k];
                     if (g.bc[axk])  // walled kernels take the default tile
                         d.ntiles = pft::spass_tiles<T>(axk == 0 ? g.nx : g.ny, 0, d.ncols);
@@ -2240,26 +2256,28 @@ pft_status batch_enqueue_group(pft_batch* b, BatchGroup& g, int slot, bool updat
     const int64_t ncols[2] = {(int64_t)g.ny * g.nz, g.nz};
     const int nslabs[2] = {1, g.nx};
     const pft::PArgs<T>* pd = static_cast<const pft::PArgs<T>*>(g.zd);
+    // Both sweeps advance together: every launch at sweep position p covers
+    // the q and the q-dagger work of all replicas of the group (D R table
+    // entries, laid out [position][pass][sweep][replica]).
+    const int DR = g.ndir * R;
     // the z pass, or the fused yz pass, at sweep position p
-    auto zlaunch = [&](int dir, int p) -> hipError_t {
-        const size_t at = ((size_t)dir * (g.maxK + 1) + p) * R;
-        if (g.fused) return pft::launch_yzpass_batch<T>(g.ny, g.nx, pd + at, R, s);
-        if (g.bc[2]) return pft::launch_zpass_walls_batch<T>(g.nz, g.bc[2], nlines, zd + at, R, s);
-        return pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + at, R, s);
+    auto zlaunch = [&](int p) -> hipError_t {
+        const size_t at = (size_t)p * DR;
+        if (g.fused) return pft::launch_yzpass_batch<T>(g.ny, g.nx, pd + at, DR, s);
+        if (g.bc[2]) return pft::launch_zpass_walls_batch<T>(g.nz, g.bc[2], nlines, zd + at, DR, s);
+        return pft::launch_zpass_batch<T>(g.nz, g.var[2], nlines, zd + at, DR, s);
     };
-    for (int dir = 0; dir < g.ndir; ++dir) {
-        PFT_BHIP(b, zlaunch(dir, 0));
-        for (int p = 0; p < g.maxK; ++p) {
-            for (int k = 0; k < g.npass; ++k) {
-                const int ax = g.sp_axis[k];
-                const pft::SArgs<T>* at = sd + (((size_t)dir * g.maxK + p) * g.npass + k) * R;
-                if (g.bc[ax])
-                    PFT_BHIP(b, pft::launch_spass_walls_batch<T>(ax, n_ax[ax], g.bc[ax], ncols[ax], nslabs[ax], at, R, s));
-                else
-                    PFT_BHIP(b, pft::launch_spass_batch<T>(ax, n_ax[ax], g.var[ax], ncols[ax], nslabs[ax], at, R, s));
-            }
-            PFT_BHIP(b, zlaunch(dir, p + 1));
+    PFT_BHIP(b, zlaunch(0));
+    for (int p = 0; p < g.maxK; ++p) {
+        for (int k = 0; k < g.npass; ++k) {
+            const int ax = g.sp_axis[k];
+            const pft::SArgs<T>* at = sd + ((size_t)p * g.npass + k) * DR;
+            if (g.bc[ax])
+                PFT_BHIP(b, pft::launch_spass_walls_batch<T>(ax, n_ax[ax], g.bc[ax], ncols[ax], nslabs[ax], at, DR, s));
+            else
+                PFT_BHIP(b, pft::launch_spass_batch<T>(ax, n_ax[ax], g.var[ax], ncols[ax], nslabs[ax], at, DR, s));
         }
+        PFT_BHIP(b, zlaunch(p + 1));
     }
     hipLaunchKernelGGL((k_sum_partials_batch<T>), dim3(64, R), dim3(kRedThreads), 0, s,
                        reinterpret_cast<const SumJob<T>*>(jb + g.off_sum));
@@ -3262,7 +3280,16 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     for (int r = 0; r < n && s == PFT_OK; ++r) {
         pft_ctx* c = nullptr;
         s = create_ctx(&params[r], hip_stream, false, &c);
-        if (s == PFT_OK) b->ctx.push_back(c);
+        if (s == PFT_OK) {
+            b->ctx.push_back(c);
+            // the conjugate sweep's work pair (both sweeps share every launch)
+            if (params[r].model != PFT_EDWARDS && !c->U2 &&
+                (hipMalloc(&c->U2, (size_t)c->M * c->elem) != hipSuccess ||
+                 hipMalloc(&c->V2, (size_t)c->M * c->elem) != hipSuccess)) {
+                (void)hipGetLastError();
+                s = PFT_E_NOMEM;
+            }
+        }
     }
     // group by grid shape, in order of first appearance
     for (int r = 0; r < n && s == PFT_OK; ++r) {
