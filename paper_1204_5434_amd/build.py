@@ -1,7 +1,8 @@
 """Build the HIP library ``libpft.so`` in-tree for gfx950 with hipcc.
 
-Each precision's axis-pass kernels and the host runtime compile as separate
-translation units in parallel, then link into one shared library.
+Each precision's axis-pass kernels and the parts of the host runtime (context,
+reverse mode, batches, autotuner) compile as separate translation units in
+parallel, then link into one shared library.
 """
 from __future__ import annotations
 
@@ -14,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpft.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["pft.hip", "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip", "passes_f32_alt.hip",
+SOURCES = ["context.hip", "adjoint.hip", "batch.hip", "tune.hip",
+           "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip", "passes_f32_alt.hip",
            "planes_f64.hip", "planes_f32.hip", "sis.hip", "passes_walls_f64.hip", "passes_walls_f32.hip",
            "stress_f64.hip", "stress_f32.hip", "stress_walls_f64.hip", "stress_walls_f32.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
