@@ -276,6 +276,32 @@ pft_status pft_cl_step(pft_ctx* ctx, double* w_plus, double* w_minus, const pft_
 pft_status pft_adjoint(pft_ctx* ctx, const double* w_plus, const double* w_minus, int32_t ckpt_every,
                        double* dH_dwplus, double* dH_dwminus, double* dH_dL, double* H);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * field step as pft_cl_step (same arguments, same kernels, same results), but
+ * the semi-implicit step (step->update = 1) takes its work memory -- the
+ * increment (M complex doubles), between reflecting walls the even image and
+ * its update (2 Me complex doubles, Me the image's sites) and the |k|^2 rows
+ * (3 x the longest image axis doubles), each block 256-byte aligned -- from a
+ * device array of PFT_STATIC_SCRATCH_BYTES inside the library instead of
+ * buffers the context allocates on first use, and fills the |k|^2 rows with a
+ * kernel instead of a host copy.  The call allocates and frees nothing (no
+ * hipMalloc, hipFree or allocating library routine).  Each GPU that the
+ * library runs on holds one copy of the array until the process ends; its
+ * address is looked up once per device (hipGetSymbolAddress), so the
+ * context's device must be current (else PFT_E_INVALID).  Limit: a step whose
+ * work memory exceeds the array is refused with PFT_E_UNSUPPORTED before
+ * anything is enqueued (periodic boxes up to 2,097,152 sites, e.g. 128^3).
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls on one stream, in order, are safe; calls that overlap in
+ * time on one GPU (other streams or other contexts without ordering between
+ * them) race on the array and give wrong fields.  The explicit step
+ * (update = 0) uses no work memory and equals pft_cl_step.  Errors: those of
+ * pft_cl_step, PFT_E_UNSUPPORTED, PFT_E_DEVICE. */
+#define PFT_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+pft_status pft_cl_step_static(pft_ctx* ctx, double* w_plus, double* w_minus, const pft_step* step,
+                              double* phi_a, double* phi_b, double* Q, double* H);
+
 /* Per-node diagnostic Qnode[j] = (1/M) sum_x q_j(x) qd_{K-j}(x), j = 0..K,
  * from the last propagate; equal to Q in exact arithmetic for every node
  * because each split step is complex-symmetric.  qnode: 2*(K+1) doubles of

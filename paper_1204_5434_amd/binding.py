@@ -35,7 +35,8 @@ EXPORTS = ("pft_create", "pft_destroy", "pft_last_error", "pft_status_string", "
            "pft_profile_end", "pft_copy_probe", "pft_adjoint", "pft_batch_create", "pft_batch_destroy",
            "pft_batch_last_error", "pft_batch_evaluate", "pft_batch_cl_steps", "pft_batch_sync",
            "pft_autotune", "pft_tune_save", "pft_tune_load", "pft_set_variant", "pft_set_concurrent_sweeps",
-           "pft_set_fused_planes", "pft_fused_planes", "pft_evaluate_graph", "pft_set_box")
+           "pft_set_fused_planes", "pft_fused_planes", "pft_evaluate_graph", "pft_set_box",
+           "pft_cl_step_static")
 
 # Kernel variants per axis length (variant 0 always exists), at most MAX_VARIANTS.
 MAX_VARIANTS = 4
@@ -96,6 +97,7 @@ def load() -> ctypes.CDLL:
             "pft_hamiltonian": (i32, [vp, vp, vp, vp, vp]),
             "pft_set_box": (i32, [vp, f64, f64, f64]),
             "pft_cl_step": (i32, [vp, vp, vp, P(pft_step), vp, vp, vp, vp]),
+            "pft_cl_step_static": (i32, [vp, vp, vp, P(pft_step), vp, vp, vp, vp]),
             "pft_node_q": (i32, [vp, vp]),
             "pft_get_slice": (i32, [vp, i32, i32, vp]),
             "pft_apply_step": (i32, [vp, i32, vp, vp]),
@@ -254,6 +256,14 @@ class Context:
                                        self._wm(w_minus), ctypes.byref(step),
                                        _opt(phi_a, self.shape, "phi_a"), _opt(phi_b, self.shape, "phi_b"),
                                        _opt(Q, (1,), "Q"), _opt(H, (1,), "H")))
+
+    def pft_cl_step_static(self, w_plus, w_minus, step: pft_step, phi_a=None, phi_b=None, Q=None, H=None):
+        """pft_cl_step with the semi-implicit step's work memory in the
+        library's fixed device array (no allocation)."""
+        self._check(load().pft_cl_step_static(self._h, _field(w_plus, self.shape, "w_plus"),
+                                              self._wm(w_minus), ctypes.byref(step),
+                                              _opt(phi_a, self.shape, "phi_a"), _opt(phi_b, self.shape, "phi_b"),
+                                              _opt(Q, (1,), "Q"), _opt(H, (1,), "H")))
 
     def pft_node_q(self, qnode):
         self._check(load().pft_node_q(self._h, _field(qnode, (self.K + 1,), "qnode")))

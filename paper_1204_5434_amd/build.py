@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpft.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["context.hip", "adjoint.hip", "batch.hip", "tune.hip",
+SOURCES = ["context.hip", "adjoint.hip", "batch.hip", "tune.hip", "static_step.hip",
            "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip", "passes_f32_alt.hip",
            "planes_f64.hip", "planes_f32.hip", "sis.hip", "passes_walls_f64.hip", "passes_walls_f32.hip",
            "stress_f64.hip", "stress_f32.hip", "stress_walls_f64.hip", "stress_walls_f32.hip"]
