@@ -723,7 +723,10 @@ def main():
         tuned = {"loaded": args.tune_file}
         log(f"[bench] kernel variants loaded from {args.tune_file}")
     elif not args.no_autotune:
-        sizes = sorted(set(w.n) | ({24, 32, 40, 48} if args.batch_replicas > 0 else set()))
+        sizes = set(w.n) | ({24, 32, 40, 48} if args.batch_replicas > 0 else set())
+        if not args.no_edwards:  # the side legs' grids: 64^3 Langevin, 96^3 reverse mode, 256^3
+            sizes |= {64, 96} | (set() if args.no_large else {256})
+        sizes = sorted(sizes)
         tuned = {}
         for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
             choice, times = binding.pft_autotune(prec, sizes)
