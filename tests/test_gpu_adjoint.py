@@ -242,3 +242,29 @@ def test_autograd_box_edges_gradcheck():
                                      L.detach().requires_grad_(True)),
                                     eps=1e-6, atol=1e-7, rtol=1e-5, fast_mode=True)
     ctx.close()
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 0, 0)])
+def test_set_box_then_semi_implicit_step(bc):
+    """After pft_set_box the semi-implicit step filters with the new box's
+    |k|^2 (its tables, built on the first step, are rebuilt): the step equals
+    that of a context created with the new edges, periodic and between
+    reflecting walls."""
+    n, ns = (16, 12, 20), 12
+    wp, wm = fields(n, 28)
+    L0, L1 = (3.0, 2.5, 4.0), (3.6, 2.2, 4.4)
+    st = B.pft_step(0.3, 1.0, 0.7, 5, 0, 2, 1, 1)
+    ctx = B.Context(B.Params(*n, *L0, ns, 0.45, 15.0, 20.0, B.PFT_C128, B.PFT_RQM4, B.PFT_DIBLOCK, 0.0,
+                             B.PFT_STORE_BOTH, bc))
+    a, b = dev(wp), dev(wm)
+    ctx.pft_cl_step(a, b, st)          # builds the filter tables for L0
+    ctx.pft_set_box(*L1)
+    a, b = dev(wp), dev(wm)
+    ctx.pft_cl_step(a, b, st)
+    ref = B.Context(B.Params(*n, *L1, ns, 0.45, 15.0, 20.0, B.PFT_C128, B.PFT_RQM4, B.PFT_DIBLOCK, 0.0,
+                             B.PFT_STORE_BOTH, bc))
+    c, d = dev(wp), dev(wm)
+    ref.pft_cl_step(c, d, st)
+    assert torch.equal(a, c) and torch.equal(b, d)
+    ctx.close()
+    ref.close()
