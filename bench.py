@@ -731,7 +731,7 @@ def main():
         tuned = {}
         for name, prec in (("f64", binding.PFT_C128), ("f32", binding.PFT_C64)):
             choice, times = binding.pft_autotune(prec, sizes)
-            tuned[name] = {str(n): {"z": c[0], "strided": c[1]} for n, c in choice.items()}
+            tuned[name] = {str(n): {"z": c[0], "x": c[1], "y": c[2]} for n, c in choice.items()}
         log(f"[bench] autotuned kernel variants: {tuned}")
         if args.tune_file:
             binding.pft_tune_save(args.tune_file)

@@ -395,14 +395,14 @@ pft_status pft_batch_sync(pft_batch* batch);
  * Every axis length has up to PFT_MAX_VARIANTS kernel variants of its passes
  * (workgroup tile width, radix split N = N1 * N2, register bound for two waves
  * per SIMD; all give the same results to rounding).  pft_autotune times every
- * variant of the z pass and of the strided passes for each listed axis length
- * on the current device (grids of ~4 Mi sites; the z pass completing and
- * starting a Richardson step, the strided kind as an x pass on both arrays
- * with its field multiply) and makes the fastest the default for
- * contexts and batches created afterwards.
- * choices (may be NULL): 2 ints per size (z variant, strided variant);
- * timings (may be NULL): 2 * PFT_MAX_VARIANTS doubles per size (ms per launch,
- * z then strided, variants 0.., -1 where a variant does not exist).
+ * variant of the z, x and y passes for each listed axis length on the current
+ * device (grids of ~4 Mi sites with lines of that length along the pass's
+ * axis; the z pass completing and starting a Richardson step, the x pass on
+ * both arrays with its field multiply, the y pass on both arrays) and makes
+ * the fastest of each the default for contexts and batches created afterwards.
+ * choices (may be NULL): 3 ints per size (z, x, y variant);
+ * timings (may be NULL): 3 * PFT_MAX_VARIANTS doubles per size (ms per launch,
+ * z then x then y, variants 0.., -1 where a variant does not exist).
  * Synchronous.
  * Errors: PFT_E_INVALID, PFT_E_UNSUPPORTED, PFT_E_NOMEM, PFT_E_DEVICE. */
 pft_status pft_autotune(int32_t precision, const int32_t* sizes, int32_t nsizes, void* hip_stream,

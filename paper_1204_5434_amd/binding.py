@@ -425,17 +425,18 @@ class Batch:
 
 def pft_autotune(precision: int, sizes):
     """Time every kernel variant for each axis length; returns
-    ({N: (z variant, strided variant)}, {N: [[z ms per variant], [strided ms per variant]]})."""
+    ({N: (z variant, x variant, y variant)},
+     {N: [[z ms per variant], [x ms per variant], [y ms per variant]]})."""
     import numpy as np
     nv = MAX_VARIANTS
     sz = np.ascontiguousarray(sizes, dtype=np.int32)
-    ch = np.zeros(2 * len(sz), dtype=np.int32)
-    tm = np.zeros(2 * nv * len(sz))
+    ch = np.zeros(3 * len(sz), dtype=np.int32)
+    tm = np.zeros(3 * nv * len(sz))
     st = load().pft_autotune(precision, sz.ctypes.data, len(sz), _stream(), ch.ctypes.data, tm.ctypes.data)
     if st != PFT_OK:
         raise PftError(st, "pft_autotune failed")
-    return ({int(n): (int(ch[2 * i]), int(ch[2 * i + 1])) for i, n in enumerate(sz)},
-            {int(n): tm[2 * nv * i:2 * nv * (i + 1)].reshape(2, nv).tolist() for i, n in enumerate(sz)})
+    return ({int(n): tuple(int(v) for v in ch[3 * i:3 * i + 3]) for i, n in enumerate(sz)},
+            {int(n): tm[3 * nv * i:3 * nv * (i + 1)].reshape(3, nv).tolist() for i, n in enumerate(sz)})
 
 
 def pft_tune_save(path: str):

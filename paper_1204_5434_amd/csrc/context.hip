@@ -507,7 +507,7 @@ pft_status create_ctx(const pft_params* params, void* hip_stream, bool dual, pft
         return PFT_E_DEVICE;
     }
     c->var[0] = tuned_variant(p.precision, p.nx, 1);
-    c->var[1] = tuned_variant(p.precision, p.ny, 1);
+    c->var[1] = tuned_variant(p.precision, p.ny, 2);
     c->var[2] = tuned_variant(p.precision, p.nz, 0);
     c->fused = fused_default(p);
     c->stream = static_cast<hipStream_t>(hip_stream);

@@ -552,7 +552,7 @@ namespace pft::rt {
 // Contour plan (see pft_contour_plan): step lengths, blocks and the junction node.
 int contour_plan(int ns, double f, double* h, int* blk, int* junction);
 // Kernel variant of an axis pass per (precision, axis length, kind: 0 = z
-// pass, 1 = strided passes) for contexts created from now on (autotuner).
+// pass, 1 = x pass, 2 = y pass) for contexts created from now on (autotuner).
 int tuned_variant(int prec, int n, int kind);
 void tune_env_once();
 pft_status create_ctx(const pft_params* params, void* hip_stream, bool dual, pft_ctx** out);

@@ -9,11 +9,11 @@
 
 namespace pft::rt {
 
-// Kernel variant per (precision, axis length, kind: 0 = z pass, 1 = strided
-// passes), used by contexts created afterwards; filled by pft_autotune or
+// Kernel variant per (precision, axis length, kind: 0 = z pass, 1 = x pass,
+// 2 = y pass), used by contexts created afterwards; filled by pft_autotune or
 // pft_tune_load (also from $PFT_TUNE_CACHE on the first pft_create).
 namespace {
-int g_tune[2][257][2] = {};
+int g_tune[2][257][3] = {};
 std::once_flag g_tune_env;
 }  // namespace
 
@@ -80,16 +80,23 @@ double time_variant(pft_ctx* c, int kind, int v, int reps)
             a.gf_n = gptr<T>(c, 0, 1, 2);
             return pft::launch_zpass<T>(c->p.nz, v, a, c->stream);
         }
-        // x pass on both arrays with the field multiply (the strided pass with
-        // the most work on chip)
         const int64_t nynz = (int64_t)c->p.ny * c->p.nz;
         pft::SArgs<T> a{};
         a.U = static_cast<cx<T>*>(c->U);
         a.V = static_cast<cx<T>*>(c->V);
-        a.opU = {gptr<T>(c, 0, 0, 0), e, gptr<T>(c, 0, 0, 0), nullptr};
-        a.opV = {gptr<T>(c, 0, 1, 0), e, nullptr, nullptr};
-        a.S = nynz;
-        return pft::launch_spass<T>(0, c->p.nx, v, nynz, a, 1, c->stream);
+        if (kind == 1) {
+            // x pass on both arrays with the field multiply
+            a.opU = {gptr<T>(c, 0, 0, 0), e, gptr<T>(c, 0, 0, 0), nullptr};
+            a.opV = {gptr<T>(c, 0, 1, 0), e, nullptr, nullptr};
+            a.S = nynz;
+            return pft::launch_spass<T>(0, c->p.nx, v, nynz, a, 1, c->stream);
+        }
+        // y pass on both arrays (the first y pass of a Richardson step)
+        a.opU = {gptr<T>(c, 0, 0, 1), nullptr, nullptr, nullptr};
+        a.opV = {gptr<T>(c, 0, 1, 1), nullptr, nullptr, nullptr};
+        a.S = c->p.nz;
+        a.slab_stride = nynz;
+        return pft::launch_spass<T>(1, c->p.ny, v, c->p.nz, a, c->p.nx, c->stream);
     };
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1;
@@ -122,13 +129,16 @@ pft_status pft_autotune(int32_t precision, const int32_t* sizes, int32_t nsizes,
     for (int i = 0; i < nsizes; ++i) {
         const int N = sizes[i];
         const int A = tune_side(N);
-        for (int kind = 0; kind < 2; ++kind) {
+        for (int kind = 0; kind < 3; ++kind) {
+            // lines of length N along z (kind 0), x (1) or y (2)
+            const int ax = kind == 0 ? 2 : kind - 1;
             pft_params p{};
-            p.nx = kind == 0 ? A : N;
-            p.ny = A;
-            p.nz = kind == 0 ? N : A;
-            p.lx = p.ly = p.lz = 0.1 * A;
-            if (kind == 0) p.lz = 0.1 * N; else p.lx = 0.1 * N;
+            p.nx = ax == 0 ? N : A;
+            p.ny = ax == 1 ? N : A;
+            p.nz = ax == 2 ? N : A;
+            p.lx = 0.1 * p.nx;
+            p.ly = 0.1 * p.ny;
+            p.lz = 0.1 * p.nz;
             p.ns = 2;
             p.f = 0.5;
             p.chiN = 10;
@@ -154,7 +164,7 @@ pft_status pft_autotune(int32_t precision, const int32_t* sizes, int32_t nsizes,
                 double ms = -1;
                 if (pft::axis_variant(N, v, &n1, &n2, &w))
                     ms = precision == PFT_C128 ? time_variant<double>(c, kind, v, 10) : time_variant<float>(c, kind, v, 10);
-                if (timings) timings[(i * 2 + kind) * PFT_MAX_VARIANTS + v] = ms;
+                if (timings) timings[(i * 3 + kind) * PFT_MAX_VARIANTS + v] = ms;
                 if (ms > 0 && (best_ms < 0 || ms < best_ms)) {
                     best_ms = ms;
                     best = v;
@@ -163,7 +173,7 @@ pft_status pft_autotune(int32_t precision, const int32_t* sizes, int32_t nsizes,
             pft_destroy(c);
             if (best_ms < 0) return PFT_E_DEVICE;
             g_tune[precision][N][kind] = best;
-            if (choices) choices[i * 2 + kind] = best;
+            if (choices) choices[i * 3 + kind] = best;
         }
     }
     return PFT_OK;
@@ -177,7 +187,7 @@ pft_status pft_tune_save(const char* path)
     const std::string arch = device_arch();
     for (int prec = 0; prec < 2; ++prec)
         for (int n = 0; n <= 256; ++n)
-            for (int kind = 0; kind < 2; ++kind)
+            for (int kind = 0; kind < 3; ++kind)
                 if (pft::axis_supported(n))
                     std::fprintf(f, "%s %d %d %d %d\n", arch.c_str(), prec, n, kind, g_tune[prec][n][kind]);
     std::fclose(f);
@@ -194,7 +204,7 @@ pft_status pft_tune_load(const char* path)
     int prec, n, kind, v;
     while (std::fscanf(f, "%63s %d %d %d %d", a, &prec, &n, &kind, &v) == 5) {
         int n1, n2, w;
-        if (arch == a && (prec == 0 || prec == 1) && (kind == 0 || kind == 1) && n >= 0 && n <= 256 &&
+        if (arch == a && (prec == 0 || prec == 1) && kind >= 0 && kind <= 2 && n >= 0 && n <= 256 &&
             pft::axis_variant(n, v, &n1, &n2, &w))
             g_tune[prec][n][kind] = v;
     }

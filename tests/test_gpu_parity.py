@@ -130,9 +130,11 @@ def test_diffusion_every_kernel_variant(orc, N):
 
 def test_autotune_roundtrip(tmp_path):
     choices, times = B.pft_autotune(B.PFT_C64, [24, 32, 48])
-    for n, (zv, sv) in choices.items():
-        assert zv in B.VARIANTS[n] and sv in B.VARIANTS[n]
-        assert min(t for t in times[n][0] if t > 0) == times[n][0][zv]
+    for n, ch in choices.items():
+        assert len(ch) == 3  # z, x, y
+        for kind, v in enumerate(ch):
+            assert v in B.VARIANTS[n]
+            assert min(t for t in times[n][kind] if t > 0) == times[n][kind][v]
     path = str(tmp_path / "tune.txt")
     B.pft_tune_save(path)
     B.pft_tune_load(path)
