@@ -377,10 +377,12 @@ def adjoint_run(binding, inputs, steps: int):
     return out
 
 
-def batched_gain(binding, inputs, count: int, steps: int):
+def batched_gain(binding, inputs, count: int, steps: int, run_steps: int):
     """Uneven replicas (grids 24-48^3, Ns 40-80): complex64 propagators, all
     replicas per launch, field steps replayed from a HIP graph -- against the
-    same replicas advanced one at a time in the plain complex128 form."""
+    same replicas advanced one at a time in the plain complex128 form.  The
+    explicit batched step is timed over a run of `run_steps` field steps (with
+    the per-step Q and H log), the other forms over `steps`."""
     import torch
     reps = inputs.batch_replicas(count, 1208)
     site_steps = sum(2.0 * w.M * w.ns for w in reps)  # per field step of the whole set
@@ -391,20 +393,26 @@ def batched_gain(binding, inputs, count: int, steps: int):
     bat = binding.Batch(params)
     wp = [torch.from_numpy(f[0]).to("cuda") for f in fields]
     wm = [torch.from_numpy(f[1]).to("cuda") for f in fields]
+    log = torch.empty((run_steps, count, 2), dtype=torch.complex128, device="cuda")
     st = binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 0, 1)
-    bat.pft_batch_cl_steps(wp, wm, st, 2)  # capture + warm-up
+    bat.pft_batch_cl_steps(wp, wm, st, 2, log)  # capture + warm-up
     bat.pft_batch_sync()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0.record()
-    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 2, 1), steps)
+    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 2, 1), run_steps, log)
     t1.record()
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
-    out["batched_c64_graph"] = {"ms_per_field_step": ms, "value": site_steps / (ms * 1e-3)}
+    ms = t0.elapsed_time(t1) / run_steps
+    H = log[:, :, 1]
+    out["batched_c64_graph"] = {"ms_per_field_step": ms, "value": site_steps / (ms * 1e-3),
+                                "field_steps": run_steps,
+                                "replicas_finite_throughout": int(torch.isfinite(H).all(dim=0).sum())}
+    del log
+    k0 = 2 + run_steps
     # the same batch with the semi-implicit field step (one filter per replica in the graph)
-    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 2 + steps, 1, 1), 1)  # capture
+    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, k0, 1, 1), 1)  # capture
     t0.record()
-    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, 3 + steps, 1, 1), steps)
+    bat.pft_batch_cl_steps(wp, wm, binding.pft_step(0.01, 1.0, 1.0, 1208, 0, k0 + 1, 1, 1), steps)
     t1.record()
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1) / steps
@@ -680,7 +688,10 @@ def main():
                     help="load the variant table from this file if it exists, else tune and save it there")
     ap.add_argument("--batch-replicas", type=int, default=256,
                     help="replicas in the batched-vs-plain comparison (0 skips it)")
-    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="field steps timed for the semi-implicit, Edwards and one-at-a-time batch forms")
+    ap.add_argument("--batch-run-steps", type=int, default=500,
+                    help="field steps of the timed explicit batched run (the run length of the workload)")
     ap.add_argument("--no-edwards", action="store_true",
                     help="skip the side measurements (other scheme, storage modes, field update, walls, adjoint, Edwards)")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 measurement")
@@ -790,7 +801,7 @@ def main():
     batched = None
     if args.batch_replicas > 0:
         log(f"[bench] batched replicas: {args.batch_replicas}, {args.batch_steps} field steps")
-        batched = batched_gain(binding, inputs, args.batch_replicas, args.batch_steps)
+        batched = batched_gain(binding, inputs, args.batch_replicas, args.batch_steps, args.batch_run_steps)
         log(f"[bench] batched: {batched}")
     cpu = cpu1 = legs = errors = None
     if not args.no_cpu_baseline:

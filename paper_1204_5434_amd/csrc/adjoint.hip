@@ -217,7 +217,6 @@ pft_status adjoint_t(pft_ctx* c, const double* wp, const double* wm, int Kc, dou
     return PFT_OK;
 }
 
-
 }  // namespace
 
 extern "C" {
@@ -239,6 +238,5 @@ pft_status pft_adjoint(pft_ctx* c, const double* wp, const double* wm, int32_t c
     return c->p.precision == PFT_C128 ? adjoint_t<double>(c, wp, wm, Kc, dwp, dwm, dL, H)
                                       : adjoint_t<float>(c, wp, wm, Kc, dwp, dwm, dL, H);
 }
-
 
 }  // extern "C"

@@ -655,5 +655,4 @@ pft_status pft_batch_sync(pft_batch* b)
     return PFT_OK;
 }
 
-
 }  // extern "C"

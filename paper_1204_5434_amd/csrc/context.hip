@@ -47,7 +47,6 @@ int contour_plan(int ns, double f, double* h, int* blk, int* junction)
     return K;
 }
 
-
 }  // namespace pft::rt
 
 namespace {
@@ -170,7 +169,6 @@ pft_status propagate_t(pft_ctx* c, const double* wp, const double* wm)
     return PFT_OK;
 }
 
-
 }  // namespace
 
 namespace pft::rt {
@@ -243,7 +241,6 @@ void free_all(pft_ctx* c)
     for (void* b : bufs)
         if (b) (void)hipFree(b);
 }
-
 
 }  // namespace pft::rt
 
@@ -450,7 +447,6 @@ pft_status diffuse_t(pft_ctx* c, double* u, double h)
     PFT_HIP(c, hipGetLastError());
     return PFT_OK;
 }
-
 
 }  // namespace
 
@@ -892,7 +888,6 @@ int32_t pft_contour_plan(int32_t ns, double f, double* h, int32_t* blk, int32_t*
     return K;
 }
 
-
 pft_status pft_create(const pft_params* params, void* hip_stream, pft_ctx** out)
 {
     return create_ctx(params, hip_stream, true, out);
@@ -912,10 +907,6 @@ pft_status pft_set_concurrent_sweeps(pft_ctx* c, int32_t on)
     return PFT_OK;
 }
 
-
-
-
-
 pft_status pft_set_fused_planes(pft_ctx* c, int32_t on)
 {
     if (!c) return PFT_E_INVALID;
@@ -928,7 +919,6 @@ pft_status pft_set_fused_planes(pft_ctx* c, int32_t on)
 }
 
 int32_t pft_fused_planes(const pft_ctx* c) { return c ? (c->fused ? (c->fused_conj_only ? 2 : 1) : 0) : -1; }
-
 
 void pft_destroy(pft_ctx* c)
 {
@@ -1057,15 +1047,6 @@ pft_status pft_hamiltonian(pft_ctx* c, const double* wp, const double* wm, doubl
     return hamiltonian_launch(c, wp, wm, H, hint);
 }
 
-
-
-
-
-
-
-
-
-
 pft_status pft_cl_step(pft_ctx* c, double* wp, double* wm, const pft_step* st, double* phi_a, double* phi_b,
                        double* Q, double* H)
 {
@@ -1136,7 +1117,6 @@ pft_status pft_status_flags(pft_ctx* c, uint32_t* flags)
     return (*flags & 1u) ? PFT_E_NONFINITE : PFT_OK;
 }
 
-
 pft_status pft_profile_begin(pft_ctx* c)
 {
     if (!c) return PFT_E_INVALID;
@@ -1178,7 +1158,6 @@ pft_status pft_copy_probe(const void* src, void* dst, int64_t bytes, void* strea
                        static_cast<const double2*>(src), static_cast<double2*>(dst), n);
     return hipGetLastError() == hipSuccess ? PFT_OK : PFT_E_DEVICE;
 }
-
 
 pft_status pft_noise_words(uint64_t seed, uint64_t rep, uint64_t step, int32_t field, int64_t M, uint64_t* out,
                            void* stream)

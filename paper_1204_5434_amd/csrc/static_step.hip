@@ -82,5 +82,4 @@ pft_status pft_cl_step_static(pft_ctx* c, double* wp, double* wm, const pft_step
     return cl_step(c, wp, wm, st, phi_a, phi_b, Q, H, &sb);
 }
 
-
 }  // extern "C"

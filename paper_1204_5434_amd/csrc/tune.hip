@@ -222,5 +222,4 @@ pft_status pft_set_variant(pft_ctx* c, int32_t axis, int32_t variant)
     return PFT_OK;
 }
 
-
 }  // extern "C"

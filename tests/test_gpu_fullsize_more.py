@@ -2,9 +2,11 @@
 configuration: the Edwards homopolymer evaluation (edw128) and the lamellar
 workload between walls (reflecting walls normal to z; absorbing walls on every
 axis).  Checked by one-step parity of the GPU's own stored slices against the
-oracle's step (the oracle cannot hold whole 128^3 sweeps quickly) and by the
-exact invariants at full size: every node pair gives Q, and the densities sum
-to the number of sites."""
+oracle's step and by the exact invariants at full size: every node pair gives
+Q, and the densities sum to the number of sites.  (The oracle's walled
+transforms follow their O(N^2) definitions, too slow for whole walled 128^3
+sweeps; the full Edwards evaluation is compared with the oracle's in
+test_gpu_fullsize_oracle.py.)"""
 import numpy as np
 import pytest
 import torch

@@ -4,6 +4,8 @@
   Eq. (12)), in the launch configuration the benchmark times: every phi_A,
   phi_B, the per-node Q and H against the oracle's complete evaluation (both
   sweeps over all 101 nodes, FP64).
+- The Edwards homopolymer workload (128^3, Ns = 100, one sweep with
+  q-dagger = q): phi, Q and H against the oracle's complete evaluation.
 - The gradient workload (96^3, Ns = 128, f = 0.3 so that the A/B junction
   falls inside a step, lamellar-plus-noise w-): dH/dw+, dH/dw- and dH/dL of the
   checkpointed reverse mode (every 11 nodes) against the oracle's reverse mode
@@ -77,6 +79,34 @@ def test_lam128_full_evaluation(lam128, prec):
         report("lam128 " + name, prec, e, bar)
     assert ea <= tol and eb <= tol
     assert eq <= tq and en <= tq and eh <= tq
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
+
+
+@pytest.fixture(scope="module")
+def edw128(orc, threads):
+    w = inputs.EDW128
+    om = inputs.fields(w)[0]
+    print("oracle: full edw128 evaluation", flush=True)
+    ref = orc.edwards_evaluate(orc.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, 0, False), w.extra["B"], om)
+    return w, om, ref
+
+
+@pytest.mark.parametrize("prec", [B.PFT_C128, B.PFT_C64])
+def test_edw128_full_evaluation(edw128, prec):
+    w, om, ref = edw128
+    ctx = B.Context(B.Params(*w.n, *w.L, w.ns, w.f, w.chiN, w.C, prec, B.PFT_RQM4, B.PFT_EDWARDS,
+                             w.extra["B"]))
+    out = ctx.evaluate(dev(om))
+    tol, tq = TOL[prec], TOL_Q[prec]
+    ep = np.abs(host(out["phiA"]) - ref["phi"]).max() / np.abs(ref["phi"]).max()
+    Q = host(out["Q"])[0]
+    eq = abs(Q - ref["Q"]) / abs(ref["Q"])
+    eh = abs(host(out["H"])[0] - ref["H"]) / (abs(ref["H"]) + w.C * np.prod(w.L))
+    for name, e, bar in (("phi", ep, tol), ("Q", eq, tq), ("H", eh, tq)):
+        report("edw128 " + name, prec, e, bar)
+    assert ep <= tol and eq <= tq and eh <= tq
+    assert np.abs(host(out["phiB"])).max() == 0.0
     assert ctx.pft_status_flags() == 0
     ctx.close()
 
