@@ -159,6 +159,14 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
     if (A.has_prev) {
         if (A.scheme == kSchemeRQM4) {
             ldc(A.U, q);
+            // Complex-float planes below 1024 lanes load V for the combine now, so
+            // that it arrives during U's transforms (256-replica batch: 43.4
+            // against 45.0 ms per field step); the 128^2 pass has no registers
+            // to spare for it (its spill grew from 64 to 84 bytes per lane and
+            // the pass slowed by 2%).
+            constexpr bool kEarlyV = std::is_same<T, float>::value && S::kPlaneThreads < 1024;
+            cx<T> v[N1];
+            if constexpr (kEarlyV) ldr(A.V, v);
             diffuse<N1, N2, true>(q, ty, sh, lay_c, A.gyh_p);
             to_rows(q);
             diffuse<N1, N2, true>(q, tz, sh, lay_r, A.gzh_p);
@@ -170,9 +178,13 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
             }
             sfor<0, N1>([&](auto I) {
                 constexpr int i = decltype(I)::value;
-                const cx<T> v = act ? Vp[ro + i * N2] : cx<T>{T(0), T(0)};
+                cx<T> vi;
+                if constexpr (kEarlyV)
+                    vi = v[i];
+                else
+                    vi = act ? Vp[ro + i * N2] : cx<T>{T(0), T(0)};
                 const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
-                q[i] = richardson(u, v);
+                q[i] = richardson(u, vi);
             });
         } else {
             ldr(A.V, q);
