@@ -495,11 +495,12 @@ def langevin_run(binding, inputs, steps: int):
     return out
 
 
-def large_grid_run(binding, inputs, steps: int):
+def large_grid_run(binding, inputs, steps: int, cl_steps: int):
     """The large single-GPU workload (256^3, Ns = 200, f = 0.35, chi N = 22,
-    L = 16, C = 100): evaluations and Langevin steps (dt = 0.005) in both
-    working precisions, per-pass bandwidth from a profiled evaluation on one
-    stream, and one checkpointed reverse-mode pass in complex64.  One 256^3
+    L = 16, C = 100): evaluations in both working precisions, its Langevin run
+    (`cl_steps` steps of dt = 0.005) in complex64 against a few complex128
+    steps, per-pass bandwidth from a profiled evaluation on one stream, and
+    one checkpointed reverse-mode pass in complex64.  One 256^3
     array is 268 MB in complex128 and 134 MB in complex64, so the passes'
     arrays no longer fit the 256 MB Infinity Cache together."""
     import torch
@@ -528,23 +529,28 @@ def large_grid_run(binding, inputs, steps: int):
         t1.record()
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1) / steps
+        # Langevin steps: the workload's whole run in complex64 (its stored form),
+        # a few steps in complex128 for the comparison; H logged per step
+        ncl = cl_steps if prec == binding.PFT_C64 else steps
         a, b = wp.clone(), wm.clone()
+        Hs = torch.empty(ncl, dtype=torch.complex128, device="cuda")
         ctx.pft_cl_step(a, b, binding.pft_step(w.dt, 1.0, 1.0, w.seed, 0, 0, 1))
         torch.cuda.synchronize()
         t0.record()
-        for k in range(steps):
-            ctx.pft_cl_step(a, b, binding.pft_step(w.dt, 1.0, 1.0, w.seed, 0, 1 + k, 1))
+        for k in range(ncl):
+            ctx.pft_cl_step(a, b, binding.pft_step(w.dt, 1.0, 1.0, w.seed, 0, 1 + k, 1), H=Hs[k:k + 1])
         t1.record()
         torch.cuda.synchronize()
-        ms_cl = t0.elapsed_time(t1) / steps
-        del a, b
+        ms_cl = t0.elapsed_time(t1) / ncl
+        h_finite = bool(torch.isfinite(Hs).all())
+        del a, b, Hs
         ctx.pft_set_concurrent_sweeps(False)
         ctx.pft_profile_begin()
         evaluate()
         prof = ctx.pft_profile_end()
         ctx.pft_set_concurrent_sweeps(True)
         res = {"ms_per_evaluation": ms, "value": 2 * w.M * w.ns / (ms * 1e-3), "ms_per_cl_step": ms_cl,
-               "device_GB": round(dev_gb, 1),
+               "cl_steps": ncl, "cl_H_finite": h_finite, "device_GB": round(dev_gb, 1),
                "kernels": {k: {"ms_per_evaluation": round(v[0], 3), "launches": int(v[1]),
                                "GB_s": round(v[2] / (v[0] * 1e-3) / 1e9, 1) if v[0] > 0 else None}
                            for k, v in prof.items() if v[1] > 0}}
@@ -695,6 +701,8 @@ def main():
     ap.add_argument("--no-edwards", action="store_true",
                     help="skip the side measurements (other scheme, storage modes, field update, walls, adjoint, Edwards)")
     ap.add_argument("--no-large", action="store_true", help="skip the 256^3 measurement")
+    ap.add_argument("--large-cl-steps", type=int, default=200,
+                    help="Langevin steps of the complex64 256^3 run (the run length of that workload)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run the library's plain copy kernel on this many MiB (counter scale)")
     args = ap.parse_args()
@@ -796,7 +804,7 @@ def main():
     large = None
     if not args.no_edwards and not args.no_large:
         log("[bench] large grid: 256^3, Ns = 200")
-        large = large_grid_run(binding, inputs, max(2, args.steps // 4))
+        large = large_grid_run(binding, inputs, max(2, args.steps // 4), args.large_cl_steps)
         log(f"[bench] large grid: {large}")
     batched = None
     if args.batch_replicas > 0:
