@@ -139,11 +139,41 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
     const int64_t base = line * N + (EXT ? 0 : t);
     const LayZ<N1, N2> lay{l};
 
+    // Walled lines with several lanes per line: the points of the walled-order
+    // register pair (i, N1-1-i) lie in one block of 2 N2 contiguous physical
+    // points (the even ones of the first, the odd ones of the second), which
+    // the lanes read and write as two contiguous runs of N2 points: in run A a
+    // lane of the line's first half takes its point of register i and a lane
+    // of the second half its point of register N1-1-i, in run B the other way
+    // round, and a select per register puts each value in place.  Every load
+    // and store instruction then covers whole 128-byte lines, as in the
+    // periodic pass, instead of every other point of two lines.
+    constexpr bool kRuns = EXT != 0 && N2 >= 2;
+    static_assert(!kRuns || N1 % 2 == 0, "register pairs need an even N1");
+    const bool hi_half = t >= N2 / 2;
+    // walled-order index of this lane's point in run B (or A) of pair i
+    auto run_n = [&](int i, bool runB) { return ((hi_half != runB) ? N1 - 1 - i : i) * N2 + t; };
+    // one point of run A or B: signed (propagator-like arrays) or not (field tables)
+    auto run_ld = [&](const cx<T>* p, int n, bool sign) -> cx<T> {
+        const cx<T> x = p[base + ext_index<EXT, N>(n)];
+        return sign ? ext_sign<EXT, N, T>(n) * x : x;
+    };
+    auto load_runs = [&](const cx<T>* p, cx<T>(&r)[N1], bool sign) {
+        sfor<0, N1 / 2>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const cx<T> a = run_ld(p, run_n(i, false), sign), b = run_ld(p, run_n(i, true), sign);
+            r[i] = hi_half ? b : a;
+            r[N1 - 1 - i] = hi_half ? a : b;
+        });
+    };
+
     // propagator-like arrays (odd points sign-flipped between absorbing walls)
     auto load = [&](const cx<T>* p, cx<T>(&r)[N1]) {
         if (act) {
             if constexpr (EXT == 0) {
                 sfor<0, N1>([&](auto I) { r[decltype(I)::value] = p[base + decltype(I)::value * N2]; });
+            } else if constexpr (kRuns) {
+                load_runs(p, r, true);
             } else {
                 sfor<0, N1>([&](auto I) {
                     const int n = decltype(I)::value * N2 + t;
@@ -159,7 +189,10 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
         if constexpr (EXT == 0) {
             load(p, r);
         } else if (act) {
-            sfor<0, N1>([&](auto I) { r[decltype(I)::value] = p[base + ext_index<EXT, N>(decltype(I)::value * N2 + t)]; });
+            if constexpr (kRuns)
+                load_runs(p, r, false);
+            else
+                sfor<0, N1>([&](auto I) { r[decltype(I)::value] = p[base + ext_index<EXT, N>(decltype(I)::value * N2 + t)]; });
         } else {
             sfor<0, N1>([&](auto I) { r[decltype(I)::value] = cx<T>{T(0), T(0)}; });
         }
@@ -168,6 +201,15 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
         if (!act) return;
         if constexpr (EXT == 0) {
             sfor<0, N1>([&](auto I) { p[base + decltype(I)::value * N2] = r[decltype(I)::value]; });
+        } else if constexpr (kRuns) {
+            sfor<0, N1 / 2>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                const int na = run_n(i, false), nb = run_n(i, true);
+                const cx<T> a = hi_half ? r[N1 - 1 - i] : r[i];
+                const cx<T> b = hi_half ? r[i] : r[N1 - 1 - i];
+                p[base + ext_index<EXT, N>(na)] = ext_sign<EXT, N, T>(na) * a;
+                p[base + ext_index<EXT, N>(nb)] = ext_sign<EXT, N, T>(nb) * b;
+            });
         } else {
             sfor<0, N1>([&](auto I) {
                 const int n = decltype(I)::value * N2 + t;
@@ -207,11 +249,23 @@ __device__ __forceinline__ void zpass_body(const ZArgs<T>& A, unsigned bid, cx<T
                 have_e = true;
             }
             if (act) {
-                sfor<0, N1>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
-                    q[i] = richardson(u, at(A.V, i));
-                });
+                if constexpr (kRuns) {
+                    // V read in contiguous runs, one register pair at a time
+                    sfor<0, N1 / 2>([&](auto I) {
+                        constexpr int i = decltype(I)::value, j = N1 - 1 - i;
+                        const cx<T> a = run_ld(A.V, run_n(i, false), true), b = run_ld(A.V, run_n(i, true), true);
+                        const cx<T> ui = A.Ep ? q[i] * e[i] : q[i];
+                        const cx<T> uj = A.Ep ? q[j] * e[j] : q[j];
+                        q[i] = richardson(ui, hi_half ? b : a);
+                        q[j] = richardson(uj, hi_half ? a : b);
+                    });
+                } else {
+                    sfor<0, N1>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
+                        q[i] = richardson(u, at(A.V, i));
+                    });
+                }
             }
         } else {
             load(A.V, q);
