@@ -81,6 +81,11 @@ struct PShape {
     static constexpr int kPWlds = kPlaneBytes >= 65536 ? 1 : int(65536 / kPlaneBytes);
     static constexpr int kPW = kPW0 < kPWlds ? kPW0 : kPWlds;
     static constexpr int kThreads = kPW * kPlaneThreads;
+    // Register bound of the batched kernel (minimum waves per SIMD): the
+    // complex-float 40^2 pass (20 x 2 lines) runs at three waves per SIMD
+    // (168 registers, a 76-byte spill) instead of two (207 registers): the
+    // 256-replica field step 41.6 -> 40.8 ms, alternating builds on one box.
+    static constexpr int kBatchMinWaves = (std::is_same<T, float>::value && N1 == 20 && N2 == 2) ? 3 : 1;
     static constexpr int64_t kLdsBytes = kPW * kPlaneBytes;
 };
 
@@ -238,7 +243,8 @@ __global__ __launch_bounds__((PShape<T, N1, N2>::kThreads)) void k_yzpass(PArgs<
 }
 
 template <typename T, int N1, int N2>
-__global__ __launch_bounds__((PShape<T, N1, N2>::kThreads)) void k_yzpass_batch(const PArgs<T>* __restrict__ descs)
+__global__ __launch_bounds__((PShape<T, N1, N2>::kThreads), (PShape<T, N1, N2>::kBatchMinWaves)) void k_yzpass_batch(
+    const PArgs<T>* __restrict__ descs)
 {
     __shared__ __align__(16) unsigned char smem_raw[PShape<T, N1, N2>::kLdsBytes];
     const PArgs<T> A = descs[blockIdx.y];
