@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 SOURCES = ["context.hip", "adjoint.hip", "batch.hip", "tune.hip", "static_step.hip",
            "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip", "passes_f32_alt.hip",
            "planes_f64.hip", "planes_f32.hip", "sis.hip", "passes_walls_f64.hip", "passes_walls_f32.hip",
-           "stress_f64.hip", "stress_f32.hip", "stress_walls_f64.hip", "stress_walls_f32.hip"]
+           "stress_f64.hip", "stress_f32.hip", "stress_walls_f64.hip", "stress_walls_f32.hip",
+           "planes_walls_f32_z0.hip", "planes_walls_f32_z1.hip", "planes_walls_f32_z2.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -42,7 +43,8 @@ def source_hash() -> str:
 KERNEL_FILES = {
     "axis": ["fft.h", "kernels.h", "passes.inc", "passes_f64.hip", "passes_f32.hip", "passes_f64_alt.hip",
              "passes_f32_alt.hip"],
-    "yzpass": ["fft.h", "kernels.h", "planes.h", "planes.inc", "planes_f64.hip", "planes_f32.hip"],
+    "yzpass": ["fft.h", "kernels.h", "planes.h", "planes.inc", "planes_f64.hip", "planes_f32.hip",
+               "planes_walls.inc", "planes_walls_f32_z0.hip", "planes_walls_f32_z1.hip", "planes_walls_f32_z2.hip"],
     "density": ["fft.h", "density.h"],
 }
 KIND_GROUP = {"zpass": "axis", "ypass": "axis", "xpass": "axis", "yzpass": "yzpass", "density": "density"}

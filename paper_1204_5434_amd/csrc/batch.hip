@@ -538,10 +538,12 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
     // group by grid shape, in order of first appearance
     for (int r = 0; r < n && s == PFT_OK; ++r) {
         const pft_params& p = params[r];
+        // the batched fused pass has no walls along y or z
+        const bool fused = b->ctx[r]->fused && !p.bc[1] && !p.bc[2];
         BatchGroup* g = nullptr;
         for (BatchGroup& x : b->groups)
             if (x.nx == p.nx && x.ny == p.ny && x.nz == p.nz && x.bc[0] == p.bc[0] && x.bc[1] == p.bc[1] &&
-                x.bc[2] == p.bc[2] && x.fused == b->ctx[r]->fused)
+                x.bc[2] == p.bc[2] && x.fused == fused)
                 g = &x;
         if (!g) {
             b->groups.emplace_back();
@@ -551,7 +553,7 @@ pft_status pft_batch_create(const pft_params* params, int32_t n, void* hip_strea
             g->nz = p.nz;
             for (int a = 0; a < 3; ++a) g->bc[a] = p.bc[a];
             g->ndir = p.model == PFT_EDWARDS ? 1 : 2;
-            g->fused = b->ctx[r]->fused;
+            g->fused = fused;
             if (g->fused) {
                 g->npass = 1;  // the x pass; the y and z work runs in the yz pass
                 g->sp_axis[0] = 0;

@@ -457,16 +457,27 @@ namespace pft::rt {
 // latency outweigh the saved passes (measured: complex double 80^2 with 244 B
 // still gains, 96^2 with 720 B loses to the axis schedule).
 constexpr int kFusedMaxSpill = 256;
+// Between walls along y or z the fused pass also holds the paired spectra of
+// its walled transforms; measured at 128^2 (complex float): with 128 spilled
+// bytes per lane (reflecting walls normal to z) it gains (10.55 against 11.00
+// ms), with 248 (absorbing walls on y and z) it loses (12.39 against 11.85).
+constexpr int kFusedMaxSpillWalls = 128;
 
+// Walls along y or z have a fused pass in complex float only.
 static bool fused_supported(const pft_params& p)
 {
-    if (p.ny != p.nz || p.bc[1] || p.bc[2]) return false;
+    if (p.ny != p.nz) return false;
+    if (p.bc[1] || p.bc[2]) return p.precision == PFT_C64 && pft::plane_walls_supported(p.ny);
     return p.precision == PFT_C128 ? pft::plane_supported<double>(p.ny) : pft::plane_supported<float>(p.ny);
 }
 
 static bool fused_default(const pft_params& p)
 {
     if (!fused_supported(p)) return false;
+    if (p.bc[1] || p.bc[2]) {
+        const int b = pft::plane_walls_private_bytes(p.ny, p.bc[1], p.bc[2]);
+        return b >= 0 && b <= kFusedMaxSpillWalls;
+    }
     const int b = p.precision == PFT_C128 ? pft::plane_private_bytes<double>(p.ny) : pft::plane_private_bytes<float>(p.ny);
     return b >= 0 && b <= kFusedMaxSpill;
 }

@@ -101,7 +101,12 @@ struct LayRow {
     __device__ __forceinline__ int operator()(int k1, int n2) const { return r * RP + k1 * (N2 + PAD) + n2; }
 };
 
-template <typename T, int N1, int N2>
+// EY, EZ: walls along y and z (0 periodic, 1 reflecting, 2 absorbing).  A
+// walled line is held in the order of pair_diffuse() (register n: physical
+// point ext_index(n), times ext_sign(n)); the reorder lives in the address
+// maps: the column layout holds y in walled order, the row layout z, and the
+// plane buffer between the two holds both axes in physical order, unsigned.
+template <typename T, int N1, int N2, int EY = 0, int EZ = 0>
 __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<T>* smem)
 {
     using S = PShape<T, N1, N2>;
@@ -119,43 +124,89 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
     const int ro = r * N + tz;
     const LayCol<N2, RP> lay_c{c};
     const LayRow<N2, RP, S::kPad ? 1 : 0> lay_r{r};
+    // physical y of column register i and physical z of row register i, with
+    // their signs (all identity without walls)
+    auto cy = [&](int i) { return ext_index<EY, N>(i * N2 + ty); };
+    auto rz = [&](int i) { return ext_index<EZ, N>(i * N2 + tz); };
+    auto sy = [&](int i) { return ext_sign<EY, N, T>(i * N2 + ty); };
+    auto sz = [&](int i) { return ext_sign<EZ, N, T>(i * N2 + tz); };
 
     auto ldc = [&](const cx<T>* p, cx<T>(&a)[N1]) {
         const cx<T>* P = p + pbase;
         if (act) {
-            sfor<0, N1>([&](auto I) { a[decltype(I)::value] = P[co + decltype(I)::value * N2 * N]; });
+            if constexpr (EY == 0)
+                sfor<0, N1>([&](auto I) { a[decltype(I)::value] = P[co + decltype(I)::value * N2 * N]; });
+            else
+                sfor<0, N1>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    a[i] = sy(i) * P[cy(i) * N + c];
+                });
         } else {
             sfor<0, N1>([&](auto I) { a[decltype(I)::value] = cx<T>{T(0), T(0)}; });
         }
     };
     auto stc = [&](cx<T>* p, const cx<T>(&a)[N1]) {
         cx<T>* P = p + pbase;
-        if (act) sfor<0, N1>([&](auto I) { P[co + decltype(I)::value * N2 * N] = a[decltype(I)::value]; });
+        if (!act) return;
+        if constexpr (EY == 0)
+            sfor<0, N1>([&](auto I) { P[co + decltype(I)::value * N2 * N] = a[decltype(I)::value]; });
+        else
+            sfor<0, N1>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                P[cy(i) * N + c] = sy(i) * a[i];
+            });
     };
-    auto ldr = [&](const cx<T>* p, cx<T>(&a)[N1]) {
+    // row layout; `sign` false for the field tables
+    auto ldr = [&](const cx<T>* p, cx<T>(&a)[N1], bool sign = true) {
         const cx<T>* P = p + pbase;
         if (act) {
-            sfor<0, N1>([&](auto I) { a[decltype(I)::value] = P[ro + decltype(I)::value * N2]; });
+            if constexpr (EZ == 0)
+                sfor<0, N1>([&](auto I) { a[decltype(I)::value] = P[ro + decltype(I)::value * N2]; });
+            else
+                sfor<0, N1>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    const cx<T> x = P[r * N + rz(i)];
+                    a[i] = sign ? sz(i) * x : x;
+                });
         } else {
             sfor<0, N1>([&](auto I) { a[decltype(I)::value] = cx<T>{T(0), T(0)}; });
         }
     };
     auto str = [&](cx<T>* p, const cx<T>(&a)[N1]) {
         cx<T>* P = p + pbase;
-        if (act) sfor<0, N1>([&](auto I) { P[ro + decltype(I)::value * N2] = a[decltype(I)::value]; });
+        if (!act) return;
+        if constexpr (EZ == 0)
+            sfor<0, N1>([&](auto I) { P[ro + decltype(I)::value * N2] = a[decltype(I)::value]; });
+        else
+            sfor<0, N1>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                P[r * N + rz(i)] = sz(i) * a[i];
+            });
     };
     // column layout -> row layout through the plane buffer, and back
     auto to_rows = [&](cx<T>(&a)[N1]) {
         __syncthreads();
-        sfor<0, N1>([&](auto I) { sh[(decltype(I)::value * N2 + ty) * RP + c] = a[decltype(I)::value]; });
+        sfor<0, N1>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            sh[cy(i) * RP + c] = sy(i) * a[i];
+        });
         __syncthreads();
-        sfor<0, N1>([&](auto I) { a[decltype(I)::value] = sh[r * RP + decltype(I)::value * N2 + tz]; });
+        sfor<0, N1>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            a[i] = sz(i) * sh[r * RP + rz(i)];
+        });
     };
     auto to_cols = [&](cx<T>(&a)[N1]) {
         __syncthreads();
-        sfor<0, N1>([&](auto I) { sh[r * RP + decltype(I)::value * N2 + tz] = a[decltype(I)::value]; });
+        sfor<0, N1>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            sh[r * RP + rz(i)] = sz(i) * a[i];
+        });
         __syncthreads();
-        sfor<0, N1>([&](auto I) { a[decltype(I)::value] = sh[(decltype(I)::value * N2 + ty) * RP + c]; });
+        sfor<0, N1>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            a[i] = sy(i) * sh[cy(i) * RP + c];
+        });
     };
 
     cx<T> q[N1];
@@ -172,13 +223,13 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
             constexpr bool kEarlyV = std::is_same<T, float>::value && S::kPlaneThreads < 1024;
             cx<T> v[N1];
             if constexpr (kEarlyV) ldr(A.V, v);
-            diffuse<N1, N2, true>(q, ty, sh, lay_c, A.gyh_p);
+            line_diffuse<EY, N1, N2, true>(q, ty, sh, lay_c, A.gyh_p);
             to_rows(q);
-            diffuse<N1, N2, true>(q, tz, sh, lay_r, A.gzh_p);
+            line_diffuse<EZ, N1, N2, true>(q, tz, sh, lay_r, A.gzh_p);
             if (A.hcap) str(A.hcap, q);
             const cx<T>* Vp = A.V + pbase;
             if (A.Ep) {
-                ldr(A.Ep, e);
+                ldr(A.Ep, e, false);
                 have_e = true;
             }
             sfor<0, N1>([&](auto I) {
@@ -186,8 +237,10 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
                 cx<T> vi;
                 if constexpr (kEarlyV)
                     vi = v[i];
-                else
+                else if constexpr (EZ == 0)
                     vi = act ? Vp[ro + i * N2] : cx<T>{T(0), T(0)};
+                else
+                    vi = act ? sz(i) * Vp[r * N + rz(i)] : cx<T>{T(0), T(0)};
                 const cx<T> u = A.Ep ? q[i] * e[i] : q[i];
                 q[i] = richardson(u, vi);
             });
@@ -195,7 +248,7 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
             ldr(A.V, q);
             if (A.hcap) str(A.hcap, q);
             if (A.Ep) {
-                ldr(A.Ep, e);
+                ldr(A.Ep, e, false);
                 have_e = true;
                 sfor<0, N1>([&](auto I) {
                     constexpr int i = decltype(I)::value;
@@ -206,14 +259,15 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
     } else if (A.qin) {
         ldr(A.qin, q);
     } else {
-        sfor<0, N1>([&](auto I) { q[decltype(I)::value] = cx<T>{T(1), T(0)}; });
+        // q = 1, in the signed walled order of the row layout
+        sfor<0, N1>([&](auto I) { q[decltype(I)::value] = sz(decltype(I)::value) * cx<T>{T(1), T(0)}; });
     }
     if (A.qout) str(A.qout, q);
 
     if (A.has_next) {
         cx<T> w[N1];
         if (A.En) {
-            if (!(have_e && A.En == A.Ep)) ldr(A.En, e);
+            if (!(have_e && A.En == A.Ep)) ldr(A.En, e, false);
             sfor<0, N1>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 q[i] = q[i] * e[i];
@@ -223,14 +277,14 @@ __device__ __forceinline__ void yzpass_body(const PArgs<T>& A, unsigned bid, cx<
             sfor<0, N1>([&](auto I) { w[decltype(I)::value] = q[decltype(I)::value]; });
         }
         if (A.scheme == kSchemeRQM4) {
-            diffuse<N1, N2, true>(q, tz, sh, lay_r, A.gzh_n);
+            line_diffuse<EZ, N1, N2, true>(q, tz, sh, lay_r, A.gzh_n);
             to_cols(q);
-            diffuse<N1, N2, true>(q, ty, sh, lay_c, A.gyh_n);
+            line_diffuse<EY, N1, N2, true>(q, ty, sh, lay_c, A.gyh_n);
             stc(A.U, q);
         }
-        diffuse<N1, N2, true>(w, tz, sh, lay_r, A.gzf_n);
+        line_diffuse<EZ, N1, N2, true>(w, tz, sh, lay_r, A.gzf_n);
         to_cols(w);
-        diffuse<N1, N2, true>(w, ty, sh, lay_c, A.gyf_n);
+        line_diffuse<EY, N1, N2, true>(w, ty, sh, lay_c, A.gyf_n);
         stc(A.V, w);
     }
 }
@@ -250,6 +304,14 @@ __global__ __launch_bounds__((PShape<T, N1, N2>::kThreads), (PShape<T, N1, N2>::
     const PArgs<T> A = descs[blockIdx.y];
     if (A.skip) return;
     yzpass_body<T, N1, N2>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
+}
+
+// The fused pass between walls along y and/or z (EY, EZ not both 0).
+template <typename T, int N1, int N2, int EY, int EZ>
+__global__ __launch_bounds__((PShape<T, N1, N2>::kThreads)) void k_yzpass_walls(PArgs<T> A)
+{
+    __shared__ __align__(16) unsigned char smem_raw[PShape<T, N1, N2>::kLdsBytes];
+    yzpass_body<T, N1, N2, EY, EZ>(A, blockIdx.x, reinterpret_cast<cx<T>*>(smem_raw));
 }
 
 // Plane sizes N (= ny = nz) with a fused kernel per precision, as (N, N1, N2):
@@ -288,6 +350,17 @@ bool plane_supported(int n);
 // n, -1 if there is none or the runtime cannot say.
 template <typename T>
 int plane_private_bytes(int n);
+
+// The walled fused pass (complex float only): whether it exists for side n,
+// its spill bytes per lane (-1: none), and its launch; ey, ez in 0..2, not
+// both 0.  Each wall kind along z is its own translation unit.
+bool plane_walls_supported(int n);
+int plane_walls_private_bytes(int n, int ey, int ez);
+hipError_t launch_yzpass_walls(int n, int ey, int ez, const PArgs<float>& a, hipStream_t s);
+template <int EZ>
+int plane_walls_private_bytes_z(int n, int ey);
+template <int EZ>
+hipError_t launch_yzpass_walls_z(int n, int ey, const PArgs<float>& a, hipStream_t s);
 
 // Launch over nx planes (a.nplanes), or over nrep replicas of one shape.
 template <typename T>

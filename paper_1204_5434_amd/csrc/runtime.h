@@ -326,6 +326,13 @@ pft_status yzpass(pft_ctx* c, int prev, int next, const cx<T>* qin, cx<T>* qout,
     if (hcap) bytes += E;
     hipStream_t st = w.stream ? w.stream : c->stream;
     ProfScope ps(c, PFT_K_YZPASS, bytes, st, true);
+    if (c->p.bc[1] || c->p.bc[2]) {
+        if constexpr (std::is_same<T, float>::value)
+            PFT_HIP(c, pft::launch_yzpass_walls(c->p.ny, c->p.bc[1], c->p.bc[2], a, st));
+        else
+            return c->fail(PFT_E_UNSUPPORTED, "no complex-double fused pass between walls");
+        return PFT_OK;
+    }
     PFT_HIP(c, pft::launch_yzpass<T>(c->p.ny, a, st));
     return PFT_OK;
 }

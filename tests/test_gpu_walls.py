@@ -3,8 +3,8 @@ sine modes, per axis) against the oracle's walled diffusion, which is written
 from the transform definitions (the GPU uses one N-point transform of the
 reordered line with paired frequencies).  Covers every line-length class
 (one lane per line up to sixteen lanes), both schemes, both precisions, the
-fused yz schedule with a walled x axis, and the calls that need a periodic
-box."""
+fused yz schedule with a walled x axis and (complex float) with walls along y
+and z, and the calls that need a periodic box."""
 import numpy as np
 import pytest
 import torch
@@ -171,6 +171,66 @@ def test_semi_implicit_edwards_step_between_reflecting_walls(orc):
     ctx.pft_cl_step(g, None, B.pft_step(0.5, 1.2, 1.0, 4, 0, 1, 1, 1), phi)
     filt = orc.edwards_sis_update(p_or, Bv, om, host(phi), 0.5, 1.2, noise=True, seed=4, replica=0, step_=1)
     assert np.abs(host(g) - filt).max() <= 1e-12 * np.abs(filt).max()
+    ctx.close()
+
+
+FUSED_WALLS = [
+    # n, L, ns, f, bc, scheme: square yz-planes with walls along y and/or z,
+    # one case per plane-split class (16 x 1, 12 x 2, 20 x 2, 12 x 4, 16 x 4, 16 x 8)
+    ((12, 16, 16), (1.5, 2.0, 2.0), 11, 0.45, (0, 0, 1), 0),
+    ((8, 24, 24), (1.0, 3.0, 3.0), 9, 0.5, (1, 2, 0), 1),
+    ((8, 40, 40), (1.0, 5.0, 5.0), 8, 0.35, (2, 1, 2), 0),
+    ((16, 48, 48), (2.0, 6.0, 6.0), 7, 0.3, (0, 2, 2), 0),
+    ((12, 64, 64), (1.5, 8.0, 8.0), 6, 0.6, (0, 1, 2), 1),
+    ((8, 128, 128), (1.0, 16.0, 16.0), 5, 0.5, (2, 1, 1), 0),
+]
+
+
+@pytest.mark.parametrize("case", FUSED_WALLS, ids=[f"{c[0]}-{c[4]}-s{c[5]}" for c in FUSED_WALLS])
+def test_walled_fused_evaluation(orc, case):
+    """The complex-float fused yz pass between walls along y and z against the
+    oracle, and against the axis schedule on the same context."""
+    n, L, ns, f, bc, scheme = case
+    say("walled fused evaluation", case)
+    r = np.random.default_rng(70 + ns)
+    wp = 0.3 * r.standard_normal(n) + 0.1j * r.standard_normal(n)
+    wm = 0.3 * r.standard_normal(n) + 0.1j * r.standard_normal(n)
+    ref = orc.evaluate(oparams(orc, n, L, ns, f, bc, scheme), wp, wm)
+    ctx = B.Context(gparams(n, L, ns, f, B.PFT_C64, bc, scheme))
+    outs = []
+    for fused in (1, 0):
+        ctx.pft_set_fused_planes(fused)
+        assert ctx.pft_fused_planes() == fused
+        outs.append({k: host(v) for k, v in ctx.evaluate(dev(wp), dev(wm)).items()})
+    V = np.prod(L)
+    tol = 2e-5
+    for out in outs:
+        for k in ("phiA", "phiB"):
+            assert np.abs(out[k] - ref[k]).max() <= tol * max(1.0, np.abs(ref[k]).max()), k
+        assert abs(out["Q"][0] - ref["Q"]) <= tol * abs(ref["Q"])
+        assert abs(out["H"][0] - ref["H"]) <= tol * (abs(ref["H"]) + 2.0 * V)
+    ctx.pft_set_fused_planes(1)
+    gp = torch.empty(n, dtype=torch.complex128, device=DEV)
+    gm = torch.empty_like(gp)
+    dL = torch.empty(3, dtype=torch.complex128, device=DEV)
+    ctx.pft_adjoint(dev(wp), dev(wm), gp, gm, dL, None, 3)
+    if n[1] in (24, 40):
+        # reverse mode through the walled fused pass (its captured pre-field
+        # values), walls along y alone and along y and z (oracle cost: seconds)
+        rp, rm, rL = orc.adjoint(oparams(orc, n, L, ns, f, bc, scheme), wp, wm)
+        assert np.abs(host(gp) - rp).max() <= tol * np.abs(rp).max()
+        assert np.abs(host(gm) - rm).max() <= tol * np.abs(rm).max()
+        C, dLh = 2.0, host(dL)
+        for a in range(3):
+            assert abs(dLh[a] - rL[a]) <= tol * (abs(rL[a]) + C * V / L[a]), (a, dLh[a], rL[a])
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
+    # complex double between walls along y or z keeps the axis schedule
+    ctx = B.Context(gparams(n, L, ns, f, B.PFT_C128, bc, scheme))
+    assert ctx.pft_fused_planes() == 0
+    with pytest.raises(B.PftError) as e:
+        ctx.pft_set_fused_planes(1)
+    assert e.value.status == B.PFT_E_UNSUPPORTED
     ctx.close()
 
 
