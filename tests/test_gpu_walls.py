@@ -234,6 +234,25 @@ def test_walled_fused_evaluation(orc, case):
     ctx.close()
 
 
+def test_walled_fused_edwards(orc):
+    """Edwards chains (one sweep, q-dagger = q) through the complex-float fused
+    yz pass between walls along y and z, against the oracle, both schedules."""
+    n, L, ns, C, Bv, bc = (8, 24, 24), (1.0, 3.0, 3.0), 14, 3.0, 1.2, (1, 2, 1)
+    say("walled fused edwards", n, bc)
+    r = np.random.default_rng(77)
+    om = 0.4 * r.standard_normal(n) + 0.1j * r.standard_normal(n)
+    ref = orc.edwards_evaluate(orc.Params(*n, *L, ns, 0.5, 1.0, C, 0, False, bc), Bv, om)
+    ctx = B.Context(B.Params(*n, *L, ns, 0.5, 1.0, C, B.PFT_C64, 0, B.PFT_EDWARDS, Bv, B.PFT_STORE_BOTH, bc))
+    tol = 2e-5
+    for fused in (1, 0):
+        ctx.pft_set_fused_planes(fused)
+        out = {k: host(v) for k, v in ctx.evaluate(dev(om)).items()}
+        assert np.abs(out["phiA"] - ref["phi"]).max() <= tol * np.abs(ref["phi"]).max(), fused
+        assert abs(out["Q"][0] - ref["Q"]) <= tol * abs(ref["Q"]), fused
+    assert ctx.pft_status_flags() == 0
+    ctx.close()
+
+
 ADJ_WALLS = [
     # n, L, ns, f, bc, scheme
     ((16, 12, 20), (2.0, 1.5, 2.5), 12, 0.41, (1, 0, 2), 0),
