@@ -84,7 +84,7 @@ struct PShape {
     // Register bound of the batched kernel (minimum waves per SIMD): the
     // complex-float 40^2 pass (20 x 2 lines) runs at three waves per SIMD
     // (168 registers, a 76-byte spill) instead of two (207 registers): the
-    // 256-replica field step 41.6 -> 40.8 ms, alternating builds on one box.
+    // 256-replica field step 41.6 -> 40.8 ms (both forms timed alternately on one device).
     static constexpr int kBatchMinWaves = (std::is_same<T, float>::value && N1 == 20 && N2 == 2) ? 3 : 1;
     static constexpr int64_t kLdsBytes = kPW * kPlaneBytes;
 };
