@@ -47,5 +47,18 @@ def test_summary_scales_and_classifies(tmp_path):
 
 def test_density_hash_ignores_host_runtime():
     # the density kernel's counters stay valid across edits of the host runtime
-    assert "pft.hip" not in build.KERNEL_FILES[build.KIND_GROUP["density"]]
-    assert "density.h" in build.KERNEL_FILES[build.KIND_GROUP["density"]]
+    density = build.KERNEL_FILES[build.KIND_GROUP["density"]]
+    assert "context.hip" not in density and "runtime.h" not in density
+    assert "density.h" in density
+
+
+def test_build_compiles_every_unit_and_hashes_existing_files():
+    # every HIP translation unit of csrc goes into the library, and every file
+    # a kernel kind's staleness hash covers exists
+    units = sorted(f for f in os.listdir(build.CSRC) if f.endswith(".hip"))
+    assert sorted(build.SOURCES) == units
+    for kind, files in build.KERNEL_FILES.items():
+        for f in files:
+            assert os.path.isfile(os.path.join(build.CSRC, f)), (kind, f)
+    # the plane-pass hash covers the walled plane kernels too
+    assert {"planes_walls.inc", "planes_walls_f32_z0.hip"} <= set(build.KERNEL_FILES["yzpass"])
